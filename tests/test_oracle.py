@@ -1,0 +1,429 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: hand-derived
+closed forms (tests/golden), exact invariants of the scheme (free stream,
+telescoping conservation, mirror symmetry, contact preservation), an
+independent global-grid formulation, textbook Riemann solutions and observed
+orders of convergence.  All run on the CPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import riemann
+from paper_2302_09005_amd import workloads as W
+from conftest import read_golden
+import _numpy_grid
+
+EPS = 2.0 ** -53
+G = 1.4
+
+
+def _step(grid, q_glob, dt, gamma=G, out_halo=True, corners=np.nan):
+    flat = grid.pack(q_glob, corners=corners)
+    desc = grid.descriptors(dt=dt, out_halo=out_halo)
+    out, me = oracle.fv_step(desc["q_in"], desc["q_out"], desc["dx"], desc["dt"], flat,
+                             grid.d, grid.p, gamma, out_halo=out_halo,
+                             out_len=grid.buffer_len(out_halo))
+    return grid.unpack(out, halo=out_halo), me
+
+
+# ---------------------------------------------------------------------------
+# closed forms (Section 2, eqs. (2), (4), (5))
+# ---------------------------------------------------------------------------
+def test_flux_hand_values():
+    rows = dict(read_golden("euler_flux_hand.txt"))
+    q = np.array(rows["state"])
+    for j, name in enumerate(("flux_x", "flux_y", "flux_z")):
+        np.testing.assert_allclose(oracle.flux(q, 3, j), np.array(rows[name]), rtol=4 * EPS, atol=0)
+    for j in range(3):
+        assert oracle.eigenvalue(q, 3, j) == pytest.approx(rows["lambda"][j], rel=2 * EPS)
+    rest = np.array(rows["rest_state"])
+    np.testing.assert_allclose(oracle.flux(rest, 3, 0), np.array(rows["rest_flux_x"]), rtol=4 * EPS, atol=0)
+    assert oracle.eigenvalue(rest, 3, 0) == pytest.approx(rows["rest_lambda"][0], rel=2 * EPS)
+    assert oracle.max_eigenvalue_state(q, 3) == pytest.approx(rows["lambda"][0], rel=2 * EPS)
+
+
+def test_flux_2d_is_3d_restricted():
+    # the 2-D flux is the 3-D one without the z-momentum row, for w = 0
+    rows = dict(read_golden("euler_flux_hand.txt"))
+    q3 = np.array(rows["state"])
+    q3[3] = 0.0
+    q3[4] = 5 / 0.4 + 0.5 * 2 * (9 + 1)
+    q2 = q3[[0, 1, 2, 4]]
+    for j in range(2):
+        f3 = oracle.flux(q3, 3, j)
+        np.testing.assert_array_equal(oracle.flux(q2, 2, j), f3[[0, 1, 2, 4]])
+
+
+def test_rusanov_sod_face_hand_value():
+    rows = dict(read_golden("rusanov_sod_face.txt"))
+    F = oracle.rusanov(rows["QL"], rows["QR"], 3, 0)
+    np.testing.assert_allclose(F, rows["F"], rtol=4 * EPS, atol=0)
+
+
+def test_rusanov_consistency_and_antisymmetry():
+    rng = np.random.default_rng(1)
+    for d in (2, 3):
+        for _ in range(20):
+            rho = rng.uniform(0.2, 2.0)
+            u = rng.uniform(-1, 1, d)
+            p = rng.uniform(0.2, 2.0)
+            q = W.to_conserved(np.array(rho), list(u), p).ravel()
+            for j in range(d):
+                # consistency: F(q, q) = f(q) exactly
+                np.testing.assert_array_equal(oracle.rusanov(q, q, d, j), oracle.flux(q, d, j))
+            q2 = W.to_conserved(np.array(rng.uniform(0.2, 2)), list(rng.uniform(-1, 1, d)),
+                                rng.uniform(0.2, 2)).ravel()
+            # reflection: F(M R, M L) = -M F(L, R) with M flipping the normal momentum
+            for j in range(d):
+                M = np.ones(d + 2)
+                M[1 + j] = -1.0
+                np.testing.assert_array_equal(oracle.rusanov(M * q2, M * q, d, j),
+                                              -M * oracle.rusanov(q, q2, d, j))
+
+
+def test_update_hand_values_shock_tube_2d():
+    rows = dict(read_golden("rusanov_sod_face.txt"))
+    F = np.array(rows["F"])[[0, 1, 2, 4]]
+    grid, q = W.grid_sod(d=2, px=4, pt=1, p=4)
+    dt = 1e-3
+    r = dt / grid.dx
+    out, _ = _step(grid, q, dt)
+    iL = grid.shape[1] // 2 - 1  # last volume left of the interface
+    got_l = out[:, 0, iL]
+    got_r = out[:, 0, iL + 1]
+    want_l = np.array([1 - r * F[0], -r * (F[1] - 1.0), 0.0, 2.5 - r * F[3]])
+    want_r = np.array([0.125 + r * F[0], -r * (0.1 - F[1]), 0.0, 0.25 + r * F[3]])
+    np.testing.assert_allclose(got_l, want_l, rtol=4 * EPS, atol=4 * EPS)
+    np.testing.assert_allclose(got_r, want_r, rtol=4 * EPS, atol=4 * EPS)
+    # volumes away from the interface keep their state exactly
+    np.testing.assert_array_equal(out[:, :, : iL - 1], q[:, :, : iL - 1])
+
+
+def test_patch_max_eigenvalue_is_of_the_new_state():
+    # Algorithm 1 ends with the patch maximum of the updated solution: for the
+    # two patches at the shock-tube interface it is set by the two updated
+    # volumes, whose states are known in closed form (hand values above).
+    rows = dict(read_golden("rusanov_sod_face.txt"))
+    F = np.array(rows["F"])[[0, 1, 2, 4]]
+    grid, q = W.grid_sod(d=2, px=4, pt=1, p=4)
+    dt = 1e-3
+    r = dt / grid.dx
+    _, me = _step(grid, q, dt)
+
+    def lam(rho, jx, E):
+        pr = (G - 1) * (E - 0.5 * jx * jx / rho)
+        return abs(jx / rho) + math.sqrt(G * pr / rho)
+
+    lam_l = max(lam(1 - r * F[0], -r * (F[1] - 1.0), 2.5 - r * F[3]), math.sqrt(G))
+    lam_r = max(lam(0.125 + r * F[0], -r * (0.1 - F[1]), 0.25 + r * F[3]), math.sqrt(G * 0.1 / 0.125))
+    assert me[1] == pytest.approx(lam_l, rel=8 * EPS) and lam_l != math.sqrt(G)
+    assert me[2] == pytest.approx(lam_r, rel=8 * EPS)
+    assert me[0] == pytest.approx(math.sqrt(G), rel=2 * EPS)
+
+
+# ---------------------------------------------------------------------------
+# invariants of the scheme
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d", [2, 3])
+def test_free_stream_is_preserved_bitwise(d):
+    state = W.to_conserved(np.array(0.7), [0.3, -0.2, 0.1][:d], 1.3).ravel()
+    grid, q = W.grid_uniform(d, (3,) * d, 4, state)
+    out, me = _step(grid, q, 0.01)
+    np.testing.assert_array_equal(out, q)
+    lam = oracle.max_eigenvalue_state(state, d)
+    np.testing.assert_array_equal(me, np.full(grid.n, lam))
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_conservation_periodic(d):
+    rng = np.random.default_rng(7)
+    p = 4
+    grid = W.PatchGrid(d, p, (3,) * d, 1.0 / (3 * p))
+    shape = grid.shape
+    rho = rng.uniform(0.5, 1.5, shape)
+    vel = [rng.uniform(-0.5, 0.5, shape) for _ in range(d)]
+    pr = rng.uniform(0.5, 2.0, shape)
+    q = W.to_conserved(rho, vel, pr)
+    per, lam = oracle.max_eigenvalue(grid.offsets(), grid.pack(q), d, p, True)
+    dt, _ = oracle.cfl_dt(np.full((grid.n, 3), grid.dx), per, d)
+    out, _ = _step(grid, q, dt)
+    for k in range(d + 2):
+        before = math.fsum(q[k].ravel())
+        after = math.fsum(out[k].ravel())
+        scale = math.fsum(np.abs(q[k]).ravel())
+        assert abs(after - before) <= 8 * EPS * scale, (k, after - before, scale)
+    # not trivially so: the state did change
+    assert np.abs(out - q).max() > 1e-3
+
+
+def test_mirror_symmetry_bitwise():
+    grid, q = W.grid_2d_smooth(4, 8, seed=3, noise=0.05)
+    # give it a velocity field so that the momentum flip matters
+    rng = np.random.default_rng(3)
+    rho = q[0]
+    u = 0.3 * np.sin(2 * np.pi * grid.cell_centres()[0])[None, :] + 0.01 * rng.standard_normal(rho.shape)
+    v = 0.2 * np.cos(2 * np.pi * grid.cell_centres()[1])[:, None] + 0.01 * rng.standard_normal(rho.shape)
+    q = W.to_conserved(rho, [u, v], 1.0 + 0.1 * rng.uniform(size=rho.shape))
+    M = np.array([1.0, -1.0, 1.0, 1.0])[:, None, None]
+    qm = M * q[:, :, ::-1]
+    out, me = _step(grid, q, 2e-3)
+    outm, mem = _step(grid, np.ascontiguousarray(qm), 2e-3)
+    np.testing.assert_array_equal(outm, M * out[:, :, ::-1])
+    # per-patch maxima: patch column i maps to column (nx-1-i)
+    nx = grid.counts[0]
+    np.testing.assert_array_equal(mem.reshape(-1, nx), me.reshape(-1, nx)[:, ::-1])
+
+
+def test_axis_swap_2d():
+    grid, q = W.grid_2d_smooth(4, 8, seed=4, noise=0.05)
+    rng = np.random.default_rng(4)
+    q = W.to_conserved(q[0], [0.2 * rng.uniform(-1, 1, q[0].shape),
+                              0.3 * rng.uniform(-1, 1, q[0].shape)], 1.0)
+    qs = np.ascontiguousarray(q[[0, 2, 1, 3]].transpose(0, 2, 1))
+    out, _ = _step(grid, q, 2e-3)
+    outs, _ = _step(grid, qs, 2e-3)
+    back = outs[[0, 2, 1, 3]].transpose(0, 2, 1)
+    # x and y terms are subtracted in the other order: equal up to rounding
+    np.testing.assert_allclose(back, out, rtol=4 * EPS, atol=4 * EPS)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_contact_wave_keeps_velocity_and_pressure(d):
+    u0 = [0.6, -0.3, 0.2][:d]
+    grid, q = W.grid_entropy_wave(d, (4,) * d, 4, u0, p0=0.8,
+                                  direction=[1, 1, 0][:d] if d == 3 else [1, 1])
+    out, _ = _step(grid, q, 3e-3)
+    assert np.abs(out[0] - q[0]).max() > 1e-4  # density did move
+    for k in range(d):
+        np.testing.assert_allclose(out[1 + k] / out[0], u0[k], rtol=0, atol=1e-14)
+    ke = 0.5 * sum(out[1 + k] * out[1 + k] for k in range(d)) / out[0]
+    np.testing.assert_allclose((G - 1) * (out[d + 1] - ke), 0.8, rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# decomposition: patches + halos == one global periodic grid, bitwise
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d,counts,p", [(2, (4, 3), 4), (3, (2, 3, 2), 4), (2, (1, 1), 6)])
+def test_patches_match_global_grid_bitwise(d, counts, p):
+    rng = np.random.default_rng(11)
+    grid = W.PatchGrid(d, p, counts, 1.0 / 32)
+    shape = grid.shape
+    q = W.to_conserved(rng.uniform(0.5, 1.5, shape),
+                       [rng.uniform(-0.5, 0.5, shape) for _ in range(d)],
+                       rng.uniform(0.5, 2.0, shape))
+    dxs = np.full(d, grid.dx)
+    # several steps through the patch machinery (update + halo fill)
+    flat = grid.pack(q)
+    off = grid.offsets()
+    nb = grid.neighbours()
+    a, t, dts = oracle.run_steps(off, np.full((grid.n, 3), grid.dx), flat, nb, d, p, 5)
+    ref = q.copy()
+    for dt in dts:
+        ref = _numpy_grid.step(ref, d, dt, dxs)
+    np.testing.assert_array_equal(grid.unpack(a), ref)
+
+
+def test_anisotropic_cells_match_global_grid_bitwise():
+    # one dx per axis and patch (the paper's cellSize is a d-vector)
+    rng = np.random.default_rng(13)
+    d, p = 3, 4
+    grid = W.PatchGrid(d, p, (2, 2, 2), 0.01)
+    q = W.to_conserved(rng.uniform(0.5, 1.5, grid.shape),
+                       [rng.uniform(-0.5, 0.5, grid.shape) for _ in range(d)],
+                       rng.uniform(0.5, 2.0, grid.shape))
+    dxs = np.array([0.01, 0.023, 0.037])
+    desc = grid.descriptors(dt=1e-3)
+    desc["dx"][:] = dxs
+    out, _ = oracle.fv_step(desc["q_in"], desc["q_out"], desc["dx"], desc["dt"], grid.pack(q),
+                            d, p, out_halo=True, out_len=grid.buffer_len(True))
+    np.testing.assert_array_equal(grid.unpack(out), _numpy_grid.step(q, d, 1e-3, dxs))
+
+
+def test_descriptor_order_and_gaps_do_not_matter():
+    grid, q = W.grid_3d_random_smooth(2, 4, seed=5)
+    rng = np.random.default_rng(5)
+    order_in = rng.permutation(grid.n)
+    order_out = rng.permutation(grid.n)
+    desc = grid.descriptors(dt=1e-3, out_halo=False, in_order=order_in, out_order=order_out, gap=7)
+    flat = grid.pack(q, order=order_in, gap=7)
+    out, me = oracle.fv_step(desc["q_in"], desc["q_out"], desc["dx"], desc["dt"], flat, 3, 4,
+                             out_halo=False, out_len=grid.buffer_len(False, 7))
+    ref, me_ref = _step(grid, q, 1e-3, out_halo=False)
+    np.testing.assert_array_equal(grid.unpack(out, halo=False, order=order_out, gap=7), ref)
+    np.testing.assert_array_equal(me, me_ref)
+
+
+def test_edge_and_corner_halo_are_never_read():
+    grid, q = W.grid_3d_random_smooth(2, 4, seed=6)
+    a, me_a = _step(grid, q, 1e-3, corners=np.nan)
+    b, me_b = _step(grid, q, 1e-3, corners=1e300)
+    assert not np.isnan(a).any()
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(me_a, me_b)
+
+
+# ---------------------------------------------------------------------------
+# halo fill, maxima, time step
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d,bc", [(2, ("periodic", "periodic")),
+                                  (2, ("transmissive", "periodic")),
+                                  (3, ("transmissive", "periodic", "transmissive")),
+                                  (3, ("periodic",) * 3)])
+def test_fill_halo_matches_global_packing(d, bc):
+    rng = np.random.default_rng(2)
+    grid = W.PatchGrid(d, 3, (3, 2, 2)[:d], 0.1, bc)
+    q = rng.standard_normal((d + 2,) + grid.shape)
+    want = grid.pack(q, corners=-7.0)
+    got = want.copy()
+    # wipe the face halos: keep interiors (and corners) only
+    interior = grid.pack(np.zeros_like(q), corners=-7.0)
+    w = grid.p + 2
+    blocks = got.reshape(grid.n, d + 2, *([w] * d))
+    mask = np.zeros([w] * d, dtype=np.int32)
+    for a in range(d):
+        sl = [slice(None)] * d
+        for e in (0, w - 1):
+            sl[a] = e
+            mask[tuple(sl)] += 1
+    blocks[:, :, mask == 1] = 12345.0
+    del interior
+    oracle.fill_halo(grid.offsets(), grid.neighbours(), got, d, grid.p)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_max_eigenvalue_piecewise_uniform_and_nan():
+    d, p = 3, 4
+    grid = W.PatchGrid(d, p, (2, 2, 1), 0.1)
+    rng = np.random.default_rng(9)
+    states, lams = [], []
+    q = np.empty((d + 2,) + grid.shape)
+    pc = grid.patch_coords()
+    for b in range(grid.n):
+        rho, pr = rng.uniform(0.5, 2), rng.uniform(0.5, 2)
+        u = rng.uniform(-1, 1, 3)
+        st = W.to_conserved(np.array(rho), list(u), pr).ravel()
+        x, y, z = pc[b]
+        q[:, z * p:(z + 1) * p, y * p:(y + 1) * p, x * p:(x + 1) * p] = st[:, None, None, None]
+        # closed form: max_j |u_j| + sqrt(gamma p / rho)
+        lams.append(np.max(np.abs(u)) + math.sqrt(G * pr / rho))
+    per, g = oracle.max_eigenvalue(grid.offsets(), grid.pack(q), d, p, True)
+    np.testing.assert_allclose(per, lams, rtol=4 * EPS)
+    assert g == max(per)
+    # negative pressure in one volume -> NaN for that patch and globally
+    bad = q.copy()
+    bad[d + 1, 0, 0, 5] = 0.0  # E = 0 with nonzero momentum -> p < 0
+    per, g = oracle.max_eigenvalue(grid.offsets(), grid.pack(bad), d, p, True)
+    assert np.isnan(per[1]) and not np.isnan(per[0]) and np.isnan(g)
+
+
+def test_cfl_dt_closed_form():
+    n, d = 5, 3
+    lam = np.array([1.0, 2.5, 0.5, 2.0, 1.5])
+    dx = np.full((n, 3), 0.01)
+    dx[2, 1] = 0.005
+    dt, L = oracle.cfl_dt(dx, lam, d, 0.4)
+    assert L == 2.5
+    assert dt == pytest.approx(0.4 * 0.005 / (3 * 2.5), rel=EPS)
+    lam[3] = np.nan
+    dt, L = oracle.cfl_dt(dx, lam, d, 0.4)
+    assert np.isnan(L) and np.isnan(dt)
+
+
+def test_cfl_factor_one_over_d_is_needed_in_3d():
+    """Reading of the CFL formula: without 1/d the unsplit 3-D update is unstable."""
+    grid = W.PatchGrid(3, 4, (2, 2, 2), 1.0 / 8)
+    rng = np.random.default_rng(12)
+    base = W.to_conserved(np.ones(grid.shape), [0.0, 0.0, 0.0], 1.0)
+    q0 = base + 1e-6 * rng.standard_normal(base.shape)
+    off, nb = grid.offsets(), grid.neighbours()
+    dx = np.full((grid.n, 3), grid.dx)
+
+    def growth(cfl):
+        a = grid.pack(q0)
+        per, _ = oracle.max_eigenvalue(off, a, 3, 4, True)
+        b = a.copy()
+        for _ in range(150):
+            dt, _ = oracle.cfl_dt(dx, per, 3, cfl)
+            b, per = oracle.fv_step(off, off, dx, np.full(grid.n, dt), a, 3, 4, q_out=b, out_halo=True)
+            oracle.fill_halo(off, nb, b, 3, 4)
+            a, b = b, a
+        return np.abs(grid.unpack(a) - base).max() / 1e-6
+
+    assert growth(0.4) < 2.0          # dt = 0.4 dx / (3 Lambda): bounded
+    assert growth(0.4 * 3) > 1e3      # dt = 0.4 dx / Lambda: unstable
+
+
+# ---------------------------------------------------------------------------
+# exact Riemann solution (textbook) and convergence of the oracle
+# ---------------------------------------------------------------------------
+def test_exact_riemann_matches_textbook_table():
+    for row in read_golden("toro_star_region.txt"):
+        left, right = tuple(row[0:3]), tuple(row[3:6])
+        p_s, u_s = riemann.star_state(left, right)
+        rl, rr = riemann.star_densities(left, right, p_s)
+        for got, want in ((p_s, row[6]), (u_s, row[7]), (rl, row[8]), (rr, row[9])):
+            assert got == pytest.approx(want, rel=1e-4, abs=1e-5)
+
+
+def test_exact_riemann_shock_satisfies_rankine_hugoniot():
+    left, right = W.SOD_LEFT, W.SOD_RIGHT
+    ws = riemann.wave_speeds(left, right)
+    S = ws["right_shock"]
+    p_s, u_s = riemann.star_state(left, right)
+    _, rr_s = riemann.star_densities(left, right, p_s)
+    qs = W.to_conserved(np.array(rr_s), [u_s, 0.0, 0.0], p_s).ravel()
+    qr = W.to_conserved(np.array(right[0]), [right[1], 0.0, 0.0], right[2]).ravel()
+    # flux jump equals shock speed times state jump (every component)
+    np.testing.assert_allclose(oracle.flux(qs, 3, 0) - oracle.flux(qr, 3, 0), S * (qs - qr),
+                               rtol=1e-12, atol=1e-12)
+    # isentropic fan: p / rho^gamma and u + 2c/(gamma-1) constant across it
+    xi = np.linspace(ws["left_head"], ws["left_tail"], 9)
+    rho, u, p = riemann.sample(left, right, xi)
+    np.testing.assert_allclose(p / rho ** G, left[2] / left[0] ** G, rtol=1e-12)
+    c = np.sqrt(G * p / rho)
+    np.testing.assert_allclose(u + 2 * c / (G - 1), 2 * math.sqrt(G) / (G - 1), rtol=1e-12)
+
+
+def _sod_l1(px, d=2, p=8, t_end=0.2):
+    grid, q = W.grid_sod(d=d, px=px, pt=1, p=p)
+    off = grid.offsets()
+    a, t, _ = oracle.run_steps(off, np.full((grid.n, 3), grid.dx), grid.pack(q),
+                               grid.neighbours(), d, p, 100000, t_end=t_end)
+    assert t == pytest.approx(t_end, abs=1e-14)
+    g = grid.unpack(a)
+    rho = g[0].reshape(-1, g.shape[-1])
+    faces = np.arange(g.shape[-1] + 1) * grid.dx
+    exact, _, _ = riemann.cell_averages(W.SOD_LEFT, W.SOD_RIGHT, faces, t_end)
+    # every row along y is the same 1-D solution, bit for bit
+    assert (rho == rho[0]).all()
+    return np.abs(rho[0] - exact).sum() * grid.dx
+
+
+def test_sod_converges_to_exact_solution():
+    errs = [_sod_l1(px) for px in (8, 16, 32, 64)]
+    assert all(e1 < e0 for e0, e1 in zip(errs, errs[1:])), errs
+    order = math.log2(errs[-2] / errs[-1])
+    assert 0.4 <= order <= 1.1, (errs, order)
+    assert errs[-1] < 0.02
+
+
+def test_smooth_wave_first_order():
+    errs = []
+    for n in (4, 8, 16):
+        u0 = [1.0, 0.0]
+        grid, q = W.grid_entropy_wave(2, (n, 1), 8, u0, p0=1.0, amp=0.2)
+        off = grid.offsets()
+        t_end = 0.25
+        a, t, _ = oracle.run_steps(off, np.full((grid.n, 3), grid.dx), grid.pack(q),
+                                   grid.neighbours(), 2, 8, 100000, t_end=t_end)
+        _, ex = W.grid_entropy_wave(2, (n, 1), 8, u0, p0=1.0, amp=0.2, t=t_end)
+        # exact cell averages of the sine: point value times sinc factor
+        fac = math.sin(math.pi * grid.dx) / (math.pi * grid.dx)
+        exact = 1.0 + (ex[0] - 1.0) * fac
+        errs.append(np.abs(grid.unpack(a)[0] - exact).mean())
+    orders = [math.log2(e0 / e1) for e0, e1 in zip(errs, errs[1:])]
+    assert all(0.8 <= o <= 1.2 for o in orders), (errs, orders)
