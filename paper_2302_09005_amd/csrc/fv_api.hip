@@ -1,0 +1,184 @@
+// C ABI of libfv (declared and documented in include/fv.h): host-side
+// argument validation, dispatch to the kernel launchers, error reporting.
+// Nothing here allocates device memory, copies to the host or synchronises.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "fv_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int ok() {
+  g_err[0] = '\0';
+  return FV_OK;
+}
+
+int64_t ipow64(int64_t b, int e) {
+  int64_t v = 1;
+  for (int i = 0; i < e; ++i) v *= b;
+  return v;
+}
+
+int check_shape(int dim, int p, int halo, int s) {
+  if (dim != 2 && dim != 3) return fail(FV_EINVAL, "dim must be 2 or 3 (got %d)", dim);
+  if (halo != 1) return fail(FV_EINVAL, "halo width must be 1 (got %d)", halo);
+  if (s != dim + 2) return fail(FV_EINVAL, "s must be dim + 2 = %d (got %d)", dim + 2, s);
+  if (p < 1) return fail(FV_EINVAL, "p must be positive (got %d)", p);
+  if (!fvk::update_supported(dim, p))
+    return fail(FV_EUNSUPPORTED, "no kernel instance for dim=%d p=%d", dim, p);
+  return FV_OK;
+}
+
+int launched(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(FV_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fv_last_error(void) { return g_err; }
+
+int fv_abi_version(void) { return 1; }
+
+int fv_supported(int dim, int p) { return fvk::update_supported(dim, p) ? 1 : 0; }
+
+int fv_check_patches(const fv_patch* host_patches, int64_t n, int dim, int p, int q_out_halo,
+                     int64_t q_in_len, int64_t q_out_len) {
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (n > 0 && !host_patches) return fail(FV_EINVAL, "patches is NULL");
+  if (dim != 2 && dim != 3) return fail(FV_EINVAL, "dim must be 2 or 3");
+  if (p < 1) return fail(FV_EINVAL, "p must be positive");
+  const int s = dim + 2;
+  const int64_t blk_in = s * ipow64(p + 2, dim);
+  const int64_t blk_out = s * (q_out_halo ? ipow64(p + 2, dim) : ipow64(p, dim));
+  for (int64_t b = 0; b < n; ++b) {
+    const fv_patch& d = host_patches[b];
+    if (d.p != p) return fail(FV_EINVAL, "patch %lld: p=%d, call p=%d", (long long)b, d.p, p);
+    if (d.q_in < 0 || d.q_in > q_in_len - blk_in)
+      return fail(FV_EINVAL, "patch %lld: input block outside q_in", (long long)b);
+    if (d.q_out < 0 || d.q_out > q_out_len - blk_out)
+      return fail(FV_EINVAL, "patch %lld: output block outside q_out", (long long)b);
+    for (int j = 0; j < dim; ++j)
+      if (!(d.dx[j] > 0.0) || !isfinite(d.dx[j]))
+        return fail(FV_EINVAL, "patch %lld: dx[%d] must be finite and > 0", (long long)b, j);
+    if (!(d.dt >= 0.0) || !isfinite(d.dt))
+      return fail(FV_EINVAL, "patch %lld: dt must be finite and >= 0", (long long)b);
+  }
+  // output blocks must be pairwise disjoint: sort a copy of the offsets and
+  // compare neighbours
+  if (n > 1) {
+    int64_t* offs = new (std::nothrow) int64_t[n];
+    if (!offs) return fail(FV_EINVAL, "out of host memory while checking overlaps");
+    for (int64_t b = 0; b < n; ++b) offs[b] = host_patches[b].q_out;
+    std::sort(offs, offs + n);
+    int64_t bad = -1;
+    for (int64_t b = 1; b < n && bad < 0; ++b)
+      if (offs[b] - offs[b - 1] < blk_out) bad = b;
+    delete[] offs;
+    if (bad >= 0) return fail(FV_EINVAL, "output blocks overlap");
+  }
+  return ok();
+}
+
+int fv_batch_update(const fv_patch* patches, int64_t n, const double* q_in, int64_t q_in_len,
+                    double* q_out, int64_t q_out_len, int q_out_halo, int dim, int p, int halo,
+                    int s, double gamma, const double* dt_dev, double* max_eig, void* stream) {
+  int rc = check_shape(dim, p, halo, s);
+  if (rc) return rc;
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (q_out_halo != 0 && q_out_halo != 1) return fail(FV_EINVAL, "q_out_halo must be 0 or 1");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (n == 0) return ok();
+  if (!patches || !q_in || !q_out) return fail(FV_EINVAL, "null device pointer");
+  if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  {
+    // the output range must not overlap the input range
+    const char* a0 = (const char*)q_in;
+    const char* a1 = a0 + q_in_len * (int64_t)sizeof(double);
+    const char* b0 = (const char*)q_out;
+    const char* b1 = b0 + q_out_len * (int64_t)sizeof(double);
+    if (a0 < b1 && b0 < a1) return fail(FV_EINVAL, "q_in and q_out overlap");
+  }
+  rc = fvk::launch_update_f64(patches, n, q_in, q_in_len, q_out, q_out_len, q_out_halo, dim, p,
+                              gamma, dt_dev, max_eig, (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  return launched("fv_batch_update");
+}
+
+int fv_max_eigenvalue(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,
+                      int q_halo, int which, int dim, int p, int s, double gamma,
+                      double* per_patch, double* global, void* stream) {
+  int rc = check_shape(dim, p, 1, s);
+  if (rc) return rc;
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (q_halo != 0 && q_halo != 1) return fail(FV_EINVAL, "q_halo must be 0 or 1");
+  if (which != FV_OFFSETS_IN && which != FV_OFFSETS_OUT)
+    return fail(FV_EINVAL, "which_offsets must be FV_OFFSETS_IN or FV_OFFSETS_OUT");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (n == 0) {
+    if (!global) return ok();
+    // nothing to reduce: the reduction kernel writes the documented 0
+    fvk::launch_reduce_cfl(patches, 0, per_patch, dim, 1.0, global, nullptr, (hipStream_t)stream);
+    return launched("fv_max_eigenvalue");
+  }
+  if (!patches || !q || !per_patch) return fail(FV_EINVAL, "null device pointer");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  rc = fvk::launch_patch_max_f64(patches, n, q, q_len, q_halo, which, dim, p, gamma, per_patch,
+                                 (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  if (global) {
+    rc = fvk::launch_reduce_cfl(patches, n, per_patch, dim, 1.0, global, nullptr,
+                                (hipStream_t)stream);
+  }
+  return launched("fv_max_eigenvalue");
+}
+
+int fv_cfl_timestep(const fv_patch* patches, int64_t n, const double* per_patch, int dim,
+                    double cfl, double* lambda_out, double* dt_out, void* stream) {
+  if (dim != 2 && dim != 3) return fail(FV_EINVAL, "dim must be 2 or 3");
+  if (n < 1) return fail(FV_EINVAL, "n_patches must be >= 1");
+  if (!(cfl > 0.0) || !isfinite(cfl)) return fail(FV_EINVAL, "cfl must be finite and > 0");
+  if (!patches || !per_patch) return fail(FV_EINVAL, "null device pointer");
+  if (!lambda_out && !dt_out) return ok();
+  fvk::launch_reduce_cfl(patches, n, per_patch, dim, cfl, lambda_out, dt_out,
+                         (hipStream_t)stream);
+  return launched("fv_cfl_timestep");
+}
+
+int fv_fill_halo(const fv_patch* patches, int64_t n, const int64_t* neighbours, double* q,
+                 int64_t q_len, int which, int dim, int p, int halo, int s, void* stream) {
+  int rc = check_shape(dim, p, halo, s);
+  if (rc) return rc;
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (which != FV_OFFSETS_IN && which != FV_OFFSETS_OUT)
+    return fail(FV_EINVAL, "which_offsets must be FV_OFFSETS_IN or FV_OFFSETS_OUT");
+  if (n == 0) return ok();
+  if (!patches || !neighbours || !q) return fail(FV_EINVAL, "null device pointer");
+  if (n * 2 * dim * (int64_t)(dim + 2) * ipow64(p, dim - 1) >= ((int64_t)1 << 39))
+    return fail(FV_EINVAL, "batch too large for one halo launch");
+  rc = fvk::launch_fill_halo_f64(patches, n, neighbours, q, q_len, which, dim, p,
+                                 (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  return launched("fv_fill_halo");
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Device-side pieces of the compressible Euler equations used by every kernel:
+// state decoding, physical flux, directional wave speed and the Rusanov face
+// flux (Section 2, eqs. (2), (4), (5) of arXiv 2302.09005).
+//
+// Unknowns (rho, j_x, j_y[, j_z], E), s = D + 2; ideal gas
+// p = (gamma - 1)(E - |j|^2 / (2 rho)).  The energy flux is (E + p) j_dir / rho
+// (the printed eq. (2) drops the factor j).  The face wave speed is the larger
+// of the two one-sided values |u_dir| + c (eq. (5) evaluated at the two
+// adjacent states).
+//
+// Rounding.  The library is built without implicit floating-point contraction;
+// the fused multiply-adds below are written out and each is invariant under a
+// sign flip of its momentum operands and under swapping the two sides of a
+// face.  Mirroring a state field therefore mirrors the result bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fvk {
+
+// Larger of a and b; NaN in either argument wins, so a blow-up reaches every
+// maximum it feeds.
+template <typename T>
+__device__ __forceinline__ T nanmax(T a, T b) {
+  return (a > b || a != a) ? a : b;
+}
+
+// What a face needs from one adjacent volume besides its conserved state:
+// 1/rho, pressure and sound speed.  Computing 1/rho once per volume replaces
+// the d + 2 divisions of the textbook formulas.
+template <typename T>
+struct Prim {
+  T ir, p, c;
+};
+
+template <typename T, int D>
+__device__ __forceinline__ Prim<T> decode(const T (&q)[D + 2], T gamma) {
+  Prim<T> w;
+  w.ir = T(1) / q[0];
+  T jj = q[1] * q[1];
+#pragma unroll
+  for (int k = 1; k < D; ++k) jj = fma(q[1 + k], q[1 + k], jj);
+  w.p = (gamma - T(1)) * fma(T(-0.5) * jj, w.ir, q[D + 1]);
+  w.c = sqrt(gamma * w.p * w.ir);
+  return w;
+}
+
+// max_j (|u_j| + c) of one volume (patch maxima and the CFL condition).
+template <typename T, int D>
+__device__ __forceinline__ T max_wave_speed(const T (&q)[D + 2], const Prim<T>& w) {
+  T m = fabs(q[1]);
+#pragma unroll
+  for (int k = 1; k < D; ++k) m = nanmax(m, T(fabs(q[1 + k])));
+  return fma(m, w.ir, w.c);
+}
+
+// Rusanov flux across a face normal to axis K between left state L and right
+// state R (Section 2, eq. (4)):
+//   F = 1/2 [ f^K(L) + f^K(R) - a (R - L) ],  a = max(|u_K(L)| + c_L, |u_K(R)| + c_R).
+template <typename T, int D, int K>
+__device__ __forceinline__ void rusanov(const T (&qL)[D + 2], const Prim<T>& wL,
+                                        const T (&qR)[D + 2], const Prim<T>& wR,
+                                        T (&F)[D + 2]) {
+  constexpr int S = D + 2;
+  const T uL = qL[1 + K] * wL.ir;
+  const T uR = qR[1 + K] * wR.ir;
+  const T a = nanmax(T(fabs(uL)) + wL.c, T(fabs(uR)) + wR.c);
+  T fL[S], fR[S];
+  fL[0] = qL[1 + K];
+  fR[0] = qR[1 + K];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    fL[1 + k] = k == K ? fma(qL[1 + k], uL, wL.p) : qL[1 + k] * uL;
+    fR[1 + k] = k == K ? fma(qR[1 + k], uR, wR.p) : qR[1 + k] * uR;
+  }
+  fL[D + 1] = (qL[D + 1] + wL.p) * uL;
+  fR[D + 1] = (qR[D + 1] + wR.p) * uR;
+#pragma unroll
+  for (int m = 0; m < S; ++m) F[m] = T(0.5) * fma(-a, qR[m] - qL[m], fL[m] + fR[m]);
+}
+
+}  // namespace fvk

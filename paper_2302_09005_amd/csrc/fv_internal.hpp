@@ -1,0 +1,60 @@
+// Internal declarations shared by the translation units of libfv (not part of
+// the C ABI): patch geometry constants and the per-kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fv.h"
+
+namespace fvk {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Geometry of a D-dimensional patch of P^D volumes with a halo of one volume,
+// and of the plane-marching update that processes it.
+//
+// The update walks the last axis (z in 3-D, y in 2-D): one lane owns one
+// column of volumes along that axis, so a patch occupies P^(D-1) lanes
+// ("LANES") and PPW patches share one workgroup when LANES < 64.
+template <int D, int P>
+struct Geo {
+  static constexpr int S = D + 2;                    // unknowns
+  static constexpr int W = P + 2;                    // volumes per axis incl. halo
+  static constexpr int VIN = ipow(W, D);             // volumes of a halo'd block
+  static constexpr int VOUT = ipow(P, D);            // volumes of a compact block
+  static constexpr int SM = ipow(W, D - 1);          // halo'd stride of the marching axis
+  static constexpr int SMO = ipow(P, D - 1);         // compact stride of the marching axis
+  static constexpr int LANES = ipow(P, D - 1);       // lanes per patch (one column each)
+  static constexpr int PPW = LANES >= 64 ? 1 : 64 / LANES;  // patches per workgroup
+  static constexpr int NT = ((PPW * LANES + 63) / 64) * 64; // workgroup size
+  static constexpr int RING = D == 3 ? 4 * P : 2;    // face-halo volumes around one plane
+  static constexpr int NEXTRA = D == 3 ? 2 * P : 1;  // in-plane faces on the high boundary
+  static constexpr int NCELL = LANES + RING;         // volumes of one plane incl. its ring
+  static constexpr int NV = S + 3;                   // values kept per volume: q, 1/rho, p, c
+  static constexpr int NF = D == 3 ? (P + 1) * P : P + 1;  // in-plane faces per axis and plane
+  static constexpr int CELLBUF = NV * NCELL;
+  static constexpr int FACEBUF = (D - 1) * S * NF;
+  static constexpr int SLOT = CELLBUF > FACEBUF ? CELLBUF : FACEBUF;  // LDS elements per patch
+  static_assert(RING <= LANES, "every ring volume needs its own lane");
+  static_assert(NEXTRA <= LANES, "every high-boundary face needs its own lane");
+};
+
+// Status for launchers: 0 ok, FV_EUNSUPPORTED when (dim, p) has no instance.
+int launch_update_f64(const fv_patch* patches, int64_t n, const double* qin, int64_t qin_len,
+                      double* qout, int64_t qout_len, int out_halo, int dim, int p,
+                      double gamma, const double* dt_dev, double* max_eig, hipStream_t st);
+
+int launch_patch_max_f64(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,
+                         int q_halo, int which, int dim, int p, double gamma,
+                         double* per_patch, hipStream_t st);
+
+int launch_reduce_cfl(const fv_patch* patches, int64_t n, const double* per_patch, int dim,
+                      double cfl, double* lambda_out, double* dt_out, hipStream_t st);
+
+int launch_fill_halo_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                         double* q, int64_t q_len, int which, int dim, int p, hipStream_t st);
+
+bool update_supported(int dim, int p);
+
+}  // namespace fvk

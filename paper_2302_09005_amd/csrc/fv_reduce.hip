@@ -1,0 +1,131 @@
+// Largest-eigenvalue reductions (Algorithm 1 last step; Section 4 of
+// arXiv 2302.09005) and the global CFL time step.
+//
+//  * patch_max_kernel: one workgroup per patch; every lane decodes volumes of
+//    the patch interior (coalesced unknown-major reads), takes
+//    max_j(|u_j| + c), and the workgroup reduces with wave shuffles and LDS.
+//  * reduce_cfl_kernel: one workgroup folds the per-patch maxima (NaN wins)
+//    and the smallest volume width into Lambda and
+//    dt = cfl * min dx / (dim * Lambda).  A single workgroup keeps the result
+//    deterministic and needs no atomics.
+#include "fv_euler.hpp"
+#include "fv_internal.hpp"
+
+namespace fvk {
+
+namespace {
+
+constexpr int kRedThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = nanmax(v, T(__shfl_xor(v, o, 64)));
+  return v;
+}
+
+template <int D, int P>
+__global__ void __launch_bounds__(kRedThreads)
+patch_max_kernel(const fv_patch* __restrict__ patches, int64_t n, const double* __restrict__ q,
+                 int64_t q_len, int q_halo, int which, double gamma,
+                 double* __restrict__ per_patch) {
+  constexpr int S = D + 2;
+  __shared__ double red[kRedThreads / 64];
+  const int64_t b = blockIdx.x;
+  if (b >= n) return;
+  const fv_patch pd = patches[b];
+  const int64_t off = which == FV_OFFSETS_OUT ? pd.q_out : pd.q_in;
+  const int w = q_halo ? P + 2 : P;
+  const int o = q_halo ? 1 : 0;
+  const int64_t vol = q_halo ? (int64_t)ipow(P + 2, D) : (int64_t)ipow(P, D);
+  const bool ok = pd.p == P && off >= 0 && off <= q_len - S * vol;
+  double lam = 0.0;
+  if (ok) {
+    const double* blk = q + off;
+    for (int i = threadIdx.x; i < ipow(P, D); i += kRedThreads) {
+      const int x = i % P;
+      const int y = (i / P) % P;
+      const int z = D == 3 ? i / (P * P) : 0;
+      const int64_t idx = (x + o) + (int64_t)w * (y + o) + (D == 3 ? (int64_t)w * w * (z + o) : 0);
+      double qv[S];
+#pragma unroll
+      for (int m = 0; m < S; ++m) qv[m] = blk[(int64_t)m * vol + idx];
+      const Prim<double> wv = decode<double, D>(qv, gamma);
+      lam = nanmax(lam, max_wave_speed<double, D>(qv, wv));
+    }
+  }
+  lam = wave_max(lam);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lam;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 1; i < kRedThreads / 64; ++i) lam = nanmax(lam, red[i]);
+    per_patch[b] = ok ? lam : __builtin_nan("");
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+reduce_cfl_kernel(const fv_patch* __restrict__ patches, int64_t n,
+                  const double* __restrict__ per_patch, int dim, double cfl,
+                  double* __restrict__ lambda_out, double* __restrict__ dt_out) {
+  __shared__ double rl[16], rh[16];
+  double lam = 0.0, h = __builtin_inf();
+  for (int64_t b = threadIdx.x; b < n; b += blockDim.x) {
+    lam = nanmax(lam, per_patch[b]);
+    for (int j = 0; j < dim; ++j) h = fmin(h, patches[b].dx[j]);
+  }
+  lam = wave_max(lam);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) h = fmin(h, __shfl_xor(h, o, 64));
+  if ((threadIdx.x & 63) == 0) {
+    rl[threadIdx.x >> 6] = lam;
+    rh[threadIdx.x >> 6] = h;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+      lam = nanmax(lam, rl[i]);
+      h = fmin(h, rh[i]);
+    }
+    if (lambda_out) *lambda_out = lam;
+    if (dt_out) *dt_out = cfl * h / ((double)dim * lam);
+  }
+}
+
+template <int D, int P>
+void launch_pm(const fv_patch* patches, int64_t n, const double* q, int64_t q_len, int q_halo,
+               int which, double gamma, double* per_patch, hipStream_t st) {
+  hipLaunchKernelGGL((patch_max_kernel<D, P>), dim3((unsigned)n), dim3(kRedThreads), 0, st,
+                     patches, n, q, q_len, q_halo, which, gamma, per_patch);
+}
+
+}  // namespace
+
+int launch_patch_max_f64(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,
+                         int q_halo, int which, int dim, int p, double gamma,
+                         double* per_patch, hipStream_t st) {
+#define FV_CASE(DD, PP)                                                                \
+  if (dim == DD && p == PP) {                                                          \
+    launch_pm<DD, PP>(patches, n, q, q_len, q_halo, which, gamma, per_patch, st);      \
+    return 0;                                                                          \
+  }
+  FV_CASE(2, 4)
+  FV_CASE(2, 8)
+  FV_CASE(2, 16)
+  FV_CASE(2, 17)
+  FV_CASE(2, 32)
+  FV_CASE(3, 4)
+  FV_CASE(3, 8)
+  FV_CASE(3, 16)
+#undef FV_CASE
+  return FV_EUNSUPPORTED;
+}
+
+int launch_reduce_cfl(const fv_patch* patches, int64_t n, const double* per_patch, int dim,
+                      double cfl, double* lambda_out, double* dt_out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_cfl_kernel, dim3(1), dim3(1024), 0, st, patches, n, per_patch, dim,
+                     cfl, lambda_out, dt_out);
+  return 0;
+}
+
+}  // namespace fvk

@@ -1,0 +1,128 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports
+every entry point include/fv.h declares, and rejects bad arguments on the host
+before anything is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2302_09005_amd import fv
+from paper_2302_09005_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^[A-Za-z_][\w \*]*?\b(fv_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function():
+    names = _declared_functions()
+    assert "fv_batch_update" in names and "fv_max_eigenvalue" in names
+    lib = fv.library()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_supported_instances():
+    assert fv.abi_version() == 1
+    for d, p in [(2, 16), (2, 17), (3, 8), (3, 4), (3, 16)]:
+        assert fv.supported(d, p)
+    for d, p in [(3, 5), (2, 3), (4, 8), (1, 8)]:
+        assert not fv.supported(d, p)
+
+
+def test_descriptor_record_matches_header():
+    src = open(os.path.join(ROOT, "include", "fv.h")).read()
+    body = re.search(r"typedef struct fv_patch \{(.*?)\} fv_patch;", src, re.S).group(1)
+    fields = re.findall(r"^\s*(int64_t|int32_t|double)\s+(\w+)(\[\d\])?;", body, re.M)
+    assert [f[1] for f in fields] == list(W.PATCH_DTYPE.names)
+
+
+def _grid_desc(out_halo=True):
+    g = W.PatchGrid(3, 8, (2, 2, 2), 1 / 16)
+    return g, g.descriptors(dt=1e-3, out_halo=out_halo)
+
+
+def test_check_patches_accepts_valid_and_names_bad_patch():
+    g, desc = _grid_desc()
+    L = g.buffer_len(True)
+    fv.check_patches(desc, 3, 8, True, L, L)
+    bad = desc.copy()
+    bad["q_in"][3] = L  # past the end
+    with pytest.raises(fv.FVError, match="patch 3"):
+        fv.check_patches(bad, 3, 8, True, L, L)
+    bad = desc.copy()
+    bad["p"][5] = 4
+    with pytest.raises(fv.FVError, match="patch 5"):
+        fv.check_patches(bad, 3, 8, True, L, L)
+    bad = desc.copy()
+    bad["q_out"][2] = bad["q_out"][1] + 8
+    with pytest.raises(fv.FVError, match="overlap"):
+        fv.check_patches(bad, 3, 8, True, L, L + 8)
+    bad = desc.copy()
+    bad["dx"][0, 1] = 0.0
+    with pytest.raises(fv.FVError, match="dx"):
+        fv.check_patches(bad, 3, 8, True, L, L)
+    bad = desc.copy()
+    bad["dt"][0] = np.nan
+    with pytest.raises(fv.FVError, match="dt"):
+        fv.check_patches(bad, 3, 8, True, L, L)
+    g2, desc2 = _grid_desc(out_halo=False)
+    fv.check_patches(desc2, 3, 8, False, L, g2.buffer_len(False))
+    with pytest.raises(fv.FVError):
+        fv.check_patches(desc2, 3, 8, False, L, g2.buffer_len(False) - 1)
+
+
+def _call_update(**kw):
+    a = dict(patches=0x1000, n=4, q_in=0x10000, q_in_len=1000, q_out=0x100000, q_out_len=1000,
+             q_out_halo=1, dim=3, p=8, halo=1, s=5, gamma=1.4, dt=None, max_eig=None, stream=None)
+    a.update(kw)
+    lib = fv.library()
+    return lib.fv_batch_update(a["patches"], a["n"], a["q_in"], a["q_in_len"], a["q_out"],
+                               a["q_out_len"], a["q_out_halo"], a["dim"], a["p"], a["halo"],
+                               a["s"], a["gamma"], a["dt"], a["max_eig"], a["stream"])
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dim=4), fv.FV_EINVAL),
+    (dict(s=4), fv.FV_EINVAL),
+    (dict(halo=2), fv.FV_EINVAL),
+    (dict(p=0), fv.FV_EINVAL),
+    (dict(p=5), fv.FV_EUNSUPPORTED),
+    (dict(n=-1), fv.FV_EINVAL),
+    (dict(gamma=1.0), fv.FV_EINVAL),
+    (dict(gamma=float("nan")), fv.FV_EINVAL),
+    (dict(q_out_halo=2), fv.FV_EINVAL),
+    (dict(patches=None), fv.FV_EINVAL),
+    (dict(q_in=None), fv.FV_EINVAL),
+    (dict(q_out=0x10000 + 8 * 500), fv.FV_EINVAL),  # q_out overlaps q_in
+])
+def test_batch_update_rejects_bad_arguments_on_host(kw, code):
+    assert _call_update(**kw) == code
+    assert fv.library().fv_last_error().decode() != ""
+
+
+def test_zero_patches_is_a_no_op_on_host():
+    assert _call_update(n=0, patches=None, q_in=None, q_out=None) == fv.FV_OK
+
+
+def test_other_entry_points_reject_bad_arguments_on_host():
+    lib = fv.library()
+    assert lib.fv_max_eigenvalue(0x1000, 4, 0x2000, 100, 1, 7, 3, 8, 5, 1.4, 0x3000, None,
+                                 None) == fv.FV_EINVAL  # bad offsets selector
+    assert lib.fv_max_eigenvalue(0x1000, 4, 0x2000, 100, 1, 0, 3, 8, 5, 1.4, None, None,
+                                 None) == fv.FV_EINVAL  # per_patch required
+    assert lib.fv_cfl_timestep(0x1000, 0, 0x2000, 3, 0.4, None, None, None) == fv.FV_EINVAL
+    assert lib.fv_cfl_timestep(0x1000, 4, 0x2000, 3, -1.0, None, None, None) == fv.FV_EINVAL
+    assert lib.fv_fill_halo(0x1000, 4, None, 0x2000, 100, 0, 3, 8, 1, 5, None) == fv.FV_EINVAL
+    assert lib.fv_fill_halo(0x1000, 4, 0x3000, 0x2000, 100, 0, 3, 3, 1, 5,
+                            None) == fv.FV_EUNSUPPORTED
