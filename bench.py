@@ -4,15 +4,17 @@
 Workload (the paper-shaped headline case): 4096 patches of 8^3 volumes (a
 periodic 128^3 domain, dx = 1/128), s = 5 unknowns, halo 1, seeded random
 smooth fields (rho in [0.5,1.5], p in [0.5,2], u in [-0.5,0.5]).  One "step"
-is the whole hot path on the device: CFL time step from the per-patch maxima
-(fv_cfl_timestep), the Rusanov update of every patch (fv_batch_update, which
-also yields the next per-patch maxima) and the face-halo exchange
-(fv_fill_halo).  Inputs are resident in HBM before the timed region starts.
+is the whole hot path on the device, in one launch (fv_step_gather): the
+Rusanov update of every patch with the face-halo exchange fused into its
+gather, the per-patch maxima of the new state and, from them, the CFL time
+step of the next step.  Inputs are resident in HBM before the timed region
+starts.  The paper's interface (halo'd blocks, update, separate halo fill) is
+timed afterwards and reported under detail.plain_halo_path.
 
 Prints ONE JSON line: cell-updates/s over the timed steps, the roofline of the
-dominant kernel (fv_batch_update; algorithmic bytes / its average duration
-measured with HIP events on the stream it runs on) and the CPU oracle timed on
-a bounded sample of the same workload.
+dominant kernel (the update; algorithmic bytes / its average duration measured
+with HIP events on the stream it runs on) and the CPU oracle timed on a
+bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu-baseline]
 """
@@ -72,6 +74,40 @@ def read_traffic():
         return None
 
 
+class HipEvents:
+    """Raw hipEvent_t pairs from the HIP runtime (for fv_set_launch_events)."""
+
+    def __init__(self, n):
+        import ctypes
+        self.ct = ctypes
+        self.lib = ctypes.CDLL("libamdhip64.so")
+        self.lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.start = [self._create() for _ in range(n)]
+        self.stop = [self._create() for _ in range(n)]
+
+    def _create(self):
+        h = self.ct.c_void_p()
+        if self.lib.hipEventCreate(self.ct.byref(h)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return h.value
+
+    def elapsed_ms(self):
+        out = []
+        for a, b in zip(self.start, self.stop):
+            ms = self.ct.c_float()
+            if self.lib.hipEventElapsedTime(self.ct.byref(ms), a, b) != 0:
+                raise RuntimeError("hipEventElapsedTime failed")
+            out.append(ms.value)
+        return np.array(out)
+
+    def destroy(self):
+        for h in self.start + self.stop:
+            self.lib.hipEventDestroy(h)
+
+
 def cpu_baseline(grid, flat, budget_s, max_steps):
     """The CPU oracle (unchanged) on a bounded sample of the same workload."""
     import oracle
@@ -93,6 +129,44 @@ def cpu_baseline(grid, flat, budget_s, max_steps):
             "sample": f"{steps} full steps (CFL + update + halo fill) of the 4096x8^3 workload, "
                       f"seed 0, plain C oracle, OpenMP over patches with {threads} threads, "
                       f"{el:.1f} s"}
+
+
+def plain_path(grid, q, steps):
+    """Steps of the paper's interface: halo'd blocks, fv_batch_update then
+    fv_fill_halo as a separate pass.  Returns per-kernel and per-step times."""
+    import torch
+    from paper_2302_09005_amd import fv
+    st = fv.Stepper(grid.descriptors(), grid.neighbours(), grid.pack(q), dim=grid.d, p=grid.p,
+                    mode="halo")
+    for _ in range(2):
+        st.step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    marks = [(ev(), ev(), ev(), ev()) for _ in range(steps)]
+    hip = HipEvents(steps)
+    for i, (e0, e1, e2, e3) in enumerate(marks):
+        e0.record(stream)
+        st.cfl_step()
+        e1.record(stream)
+        fv.set_launch_events(hip.start[i], hip.stop[i])
+        st.update()
+        fv.set_launch_events(None, None)
+        e2.record(stream)
+        st.exchange()
+        e3.record(stream)
+        st.swap()
+    torch.cuda.synchronize()
+    step_ms = np.array([a.elapsed_time(e) for a, _, _, e in marks])
+    upd_ms = hip.elapsed_ms()
+    hip.destroy()
+    halo_ms = np.array([c.elapsed_time(e) for _, _, c, e in marks])
+    cfl_ms = np.array([a.elapsed_time(b) for a, b, _, _ in marks])
+    bpc = algorithmic_bytes_per_cell(grid.d, grid.p, grid.s, 8)
+    return {"steps": steps, "cell_updates_per_s": grid.cells / (step_ms.mean() * 1e-3),
+            "update_us": float(upd_ms.mean() * 1e3), "halo_fill_us": float(halo_ms.mean() * 1e3),
+            "cfl_us": float(cfl_ms.mean() * 1e3),
+            "update_hbm_frac": bpc * grid.cells / (upd_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def copy_calibration(mib=1024, reps=5):
@@ -123,8 +197,8 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(patches would be sharded across GPUs with a face-halo exchange; "
-              "see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+              "(patches would be sharded across GPUs with a face-halo exchange "
+              "between partitions). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -139,42 +213,41 @@ def main():
     from paper_2302_09005_amd import workloads as W
 
     grid, q = W.grid_3d_random_smooth(16, 8, seed=args.seed)
-    flat = grid.pack(q)
     d, p, s = grid.d, grid.p, grid.s
-    st = fv.Stepper(grid.descriptors(), grid.neighbours(), flat, dim=d, p=p)
+    desc = grid.descriptors(out_halo=False, in_halo=False)
+    st = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=d, p=p, mode="fused")
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
         st.step()
     torch.cuda.synchronize()
 
+    # Per-launch kernel time: HIP events recorded by the update's own dispatch
+    # packet (fv_set_launch_events), i.e. the kernel's execution on the stream
+    # it runs on; the whole timed region is bracketed by torch events.
+    hip = HipEvents(args.steps)
     stream = torch.cuda.current_stream()
-    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    marks = [(ev(), ev(), ev(), ev()) for _ in range(args.steps)]
-    t_start, t_end = ev(), ev()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
-    for (e0, e1, e2, e3) in marks:
-        e0.record(stream)
-        fv.cfl_timestep(st.patches, st.per_patch, dim=d, cfl=st.cfl, lambda_out=st.lam,
-                        dt_out=st.dt)
-        e1.record(stream)
-        fv.batch_update(st.patches, st.a, st.b, dim=d, p=p, gamma=st.gamma, q_out_halo=True,
-                        dt=st.dt, max_eig=st.per_patch)
-        e2.record(stream)
-        fv.fill_halo(st.patches, st.neighbours, st.b, dim=d, p=p)
-        e3.record(stream)
-        st.a, st.b = st.b, st.a
+    for i in range(args.steps):
+        fv.set_launch_events(hip.start[i], hip.stop[i])
+        st.update()
+        st.swap()
+    fv.set_launch_events(None, None)
     t_end.record(stream)
     torch.cuda.synchronize()
 
     total_ms = t_start.elapsed_time(t_end)
-    cfl_ms = np.array([a.elapsed_time(b) for a, b, _, _ in marks])
-    upd_ms = np.array([b.elapsed_time(c) for _, b, c, _ in marks])
-    halo_ms = np.array([c.elapsed_time(e) for _, _, c, e in marks])
+    upd_ms = hip.elapsed_ms()
+    hip.destroy()
     state = st.state()
-    finite = bool(torch.isfinite(state[~torch.isnan(state)]).all().item())
+    finite = bool(torch.isfinite(state).all().item())
     lam_final = st.lam.item()
+
+    # the paper's interface for comparison: halo'd blocks, update + separate halo fill
+    plain = plain_path(grid, q, min(args.steps, 20))
 
     cells = grid.cells
     value = cells * args.steps / (total_ms * 1e-3)
@@ -198,20 +271,19 @@ def main():
         "data": "synthetic (seeded random smooth 3-D Euler fields)",
         "config": {"workload": "3d-euler-fp64-4096x8^3-periodic", "patches": grid.n, "p": p,
                    "d": d, "s": s, "halo": 1, "dx": grid.dx, "cfl": st.cfl, "seed": args.seed,
-                   "step": "cfl_timestep + batch_update + fill_halo"},
+                   "step": "fv_step_gather: update + halo exchange + next CFL step, one launch"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fv_update_kernel<double,3,8>",
+                     "kernel": "fv_update_kernel<double,3,8,GATHER,CFL>",
                      "algorithmic_bytes_per_cell": bpc,
                      "kernel_avg_us": upd_ms.mean() * 1e3},
         "detail": {"update_cell_updates_per_s": cells / upd_s,
                    "update_us_median": float(np.median(upd_ms) * 1e3),
-                   "halo_us_mean": float(halo_ms.mean() * 1e3),
-                   "cfl_us_mean": float(cfl_ms.mean() * 1e3),
-                   "final_lambda": lam_final, "state_finite": finite},
+                   "final_lambda": lam_final, "state_finite": finite,
+                   "plain_halo_path": plain},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(grid, flat, args.cpu_budget, 100)
+        out["cpu_baseline"] = cpu_baseline(grid, grid.pack(q), args.cpu_budget, 100)
     print(json.dumps(out), flush=True)
 
 

@@ -77,14 +77,25 @@ int fv_abi_version(void);
 int fv_supported(int dim, int p);
 
 /*
+ * Kernel timing: until called again, every update launch of the calling
+ * thread (fv_batch_update, fv_batch_update_gather, fv_step_gather) has its
+ * dispatch record start_event when the kernel begins and stop_event when it
+ * ends (hipEvent_t handles created by the caller), so the elapsed time
+ * between them is the kernel's execution alone.  Pass two NULLs to stop.
+ * Returns FV_EINVAL if exactly one is NULL.
+ */
+int fv_set_launch_events(void* start_event, void* stop_event);
+
+/*
  * Host-side validation of a descriptor array (a HOST copy), for callers that
  * build descriptors themselves.  Checks p, finite positive dx and dt >= 0,
- * that every input/output block lies inside [0, len), and that output blocks
- * do not overlap each other.  Returns FV_OK or FV_EINVAL (with the first
+ * that every input/output block lies inside [0, len) (q_in_halo/q_out_halo:
+ * 1 for blocks [s][(p+2)^d], 0 for [s][p^d]), and that output blocks do not
+ * overlap each other.  Returns FV_OK or FV_EINVAL (with the first
  * offending patch named by fv_last_error()).  Touches no device.
  */
 int fv_check_patches(const fv_patch* host_patches, int64_t n_patches,
-                     int dim, int p, int q_out_halo,
+                     int dim, int p, int q_in_halo, int q_out_halo,
                      int64_t q_in_len, int64_t q_out_len);
 
 /*
@@ -122,6 +133,66 @@ int fv_batch_update(const fv_patch* patches, int64_t n_patches,
                     double* q_out, int64_t q_out_len, int q_out_halo,
                     int dim, int p, int halo, int s, double gamma,
                     const double* dt_dev, double* max_eig, void* stream);
+
+/*
+ * fv_batch_update_gather -- the same step as fv_batch_update, with the
+ * face-halo exchange fused into the gather (Section 2: keeping the halo
+ * consistent is the engine's job; here it is done while the tiles are read).
+ * Patch blocks carry NO halo: q_in holds [s][p^d] at patches[b].q_in, and
+ * each face-halo volume the update needs is read from the facing interior
+ * volume of the neighbouring patch.  The result equals fv_fill_halo followed
+ * by fv_batch_update on the same data stored with halos.
+ *
+ * neighbours  device int64 [n_patches][2*dim], face order -x, +x, -y, +y,
+ *             -z, +z; entries in [0, n_patches) (periodic domains use
+ *             wrapped indices) or -1 for a transmissive (zero-gradient)
+ *             boundary, where the patch's own boundary volume is used.
+ * q_out       [s][p^d] (q_out_halo == 0) or [s][(p+2)^d] (== 1, interior
+ *             written) at patches[b].q_out; must not overlap q_in.
+ * Other arguments as for fv_batch_update.  A patch whose own or neighbour
+ * descriptors fail the device-side check (p mismatch, block outside q_in,
+ * neighbour index outside [-1, n_patches)) is not updated and gets NaN in
+ * max_eig.
+ */
+int fv_batch_update_gather(const fv_patch* patches, int64_t n_patches,
+                           const int64_t* neighbours,
+                           const double* q_in, int64_t q_in_len,
+                           double* q_out, int64_t q_out_len, int q_out_halo,
+                           int dim, int p, int s, double gamma,
+                           const double* dt_dev, double* max_eig, void* stream);
+
+/*
+ * fv_step_gather -- one whole explicit step of the batch in ONE launch: the
+ * update of fv_batch_update_gather (compact blocks, halo exchange fused into
+ * the gather) and the CFL time step of the next step, computed from the
+ * per-patch maxima of the new state exactly as fv_cfl_timestep does
+ * (Lambda = max_b max_eig[b], dt = cfl * min dx / (dim * Lambda)).
+ *
+ * dt_dev      device [1]: the time step of THIS step (required)
+ * max_eig     device [n_patches] or NULL: per-patch maxima of the new state
+ * dt_next     device [1]: the time step for the next step (required; must not
+ *             alias dt_dev -- alternate two buffers between steps)
+ * lambda_out  device [1] or NULL: Lambda of the new state
+ * workspace   device uint64 [workspace_words], at least
+ *             fv_step_workspace_words(n_patches, dim, p) words (FV_EINVAL
+ *             otherwise), all zero before the first call; every call leaves
+ *             it zero again.  Calls that overlap in time (different streams)
+ *             must use different workspaces.
+ * q_out is [s][p^d] (compact).  Other arguments as for
+ * fv_batch_update_gather.  The reduction is an integer maximum of IEEE bit
+ * patterns (all values are >= 0 or NaN), so the result does not depend on the
+ * order in which workgroups finish; a NaN maximum gives a NaN time step.
+ */
+int fv_step_gather(const fv_patch* patches, int64_t n_patches, const int64_t* neighbours,
+                   const double* q_in, int64_t q_in_len, double* q_out, int64_t q_out_len,
+                   int dim, int p, int s, double gamma, double cfl,
+                   const double* dt_dev, double* max_eig, double* dt_next,
+                   double* lambda_out, uint64_t* workspace, int64_t workspace_words,
+                   void* stream);
+
+/* Size in uint64 words of the workspace fv_step_gather needs (0 on bad
+ * arguments).  A few words per 64 workgroups: small, allocate once. */
+int64_t fv_step_workspace_words(int64_t n_patches, int dim, int p);
 
 /*
  * fv_max_eigenvalue -- largest eigenvalue of a given state (Section 2,

@@ -14,6 +14,7 @@
 namespace {
 
 thread_local char g_err[512] = "";
+thread_local fvk::LaunchEvents g_events;
 
 int fail(int code, const char* fmt, ...) {
   va_list ap;
@@ -52,7 +53,20 @@ int launched(const char* what) {
 
 }  // namespace
 
+namespace fvk {
+LaunchEvents& launch_events() { return g_events; }
+}  // namespace fvk
+
 extern "C" {
+
+int fv_set_launch_events(void* start_event, void* stop_event) {
+  if ((start_event == nullptr) != (stop_event == nullptr))
+    return fail(FV_EINVAL, "give both events or neither");
+  g_events.start = (hipEvent_t)start_event;
+  g_events.stop = (hipEvent_t)stop_event;
+  return ok();
+}
+
 
 const char* fv_last_error(void) { return g_err; }
 
@@ -60,14 +74,14 @@ int fv_abi_version(void) { return 1; }
 
 int fv_supported(int dim, int p) { return fvk::update_supported(dim, p) ? 1 : 0; }
 
-int fv_check_patches(const fv_patch* host_patches, int64_t n, int dim, int p, int q_out_halo,
-                     int64_t q_in_len, int64_t q_out_len) {
+int fv_check_patches(const fv_patch* host_patches, int64_t n, int dim, int p, int q_in_halo,
+                     int q_out_halo, int64_t q_in_len, int64_t q_out_len) {
   if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
   if (n > 0 && !host_patches) return fail(FV_EINVAL, "patches is NULL");
   if (dim != 2 && dim != 3) return fail(FV_EINVAL, "dim must be 2 or 3");
   if (p < 1) return fail(FV_EINVAL, "p must be positive");
   const int s = dim + 2;
-  const int64_t blk_in = s * ipow64(p + 2, dim);
+  const int64_t blk_in = s * (q_in_halo ? ipow64(p + 2, dim) : ipow64(p, dim));
   const int64_t blk_out = s * (q_out_halo ? ipow64(p + 2, dim) : ipow64(p, dim));
   for (int64_t b = 0; b < n; ++b) {
     const fv_patch& d = host_patches[b];
@@ -122,6 +136,73 @@ int fv_batch_update(const fv_patch* patches, int64_t n, const double* q_in, int6
                               gamma, dt_dev, max_eig, (hipStream_t)stream);
   if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
   return launched("fv_batch_update");
+}
+
+int fv_batch_update_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                           const double* q_in, int64_t q_in_len, double* q_out,
+                           int64_t q_out_len, int q_out_halo, int dim, int p, int s,
+                           double gamma, const double* dt_dev, double* max_eig, void* stream) {
+  int rc = check_shape(dim, p, 1, s);
+  if (rc) return rc;
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (q_out_halo != 0 && q_out_halo != 1) return fail(FV_EINVAL, "q_out_halo must be 0 or 1");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (n == 0) return ok();
+  if (!patches || !neighbours || !q_in || !q_out) return fail(FV_EINVAL, "null device pointer");
+  if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  {
+    const char* a0 = (const char*)q_in;
+    const char* a1 = a0 + q_in_len * (int64_t)sizeof(double);
+    const char* b0 = (const char*)q_out;
+    const char* b1 = b0 + q_out_len * (int64_t)sizeof(double);
+    if (a0 < b1 && b0 < a1) return fail(FV_EINVAL, "q_in and q_out overlap");
+  }
+  rc = fvk::launch_update_gather_f64(patches, n, neighbours, q_in, q_in_len, q_out, q_out_len,
+                                     q_out_halo, dim, p, gamma, dt_dev, max_eig,
+                                     (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  return launched("fv_batch_update_gather");
+}
+
+int64_t fv_step_workspace_words(int64_t n, int dim, int p) {
+  if (n < 1 || !fvk::update_supported(dim, p)) return 0;
+  return fvk::step_workspace_words(fvk::update_workgroups(dim, p, n));
+}
+
+int fv_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                   const double* q_in, int64_t q_in_len, double* q_out, int64_t q_out_len,
+                   int dim, int p, int s, double gamma, double cfl, const double* dt_dev,
+                   double* max_eig, double* dt_next, double* lambda_out, uint64_t* workspace,
+                   int64_t workspace_words, void* stream) {
+  int rc = check_shape(dim, p, 1, s);
+  if (rc) return rc;
+  if (n < 1) return fail(FV_EINVAL, "n_patches must be >= 1");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (!(cfl > 0.0) || !isfinite(cfl)) return fail(FV_EINVAL, "cfl must be finite and > 0");
+  if (!patches || !neighbours || !q_in || !q_out || !dt_dev || !dt_next || !workspace)
+    return fail(FV_EINVAL, "null device pointer");
+  if (dt_next == dt_dev) return fail(FV_EINVAL, "dt_next must not alias dt_dev");
+  if (workspace_words < fv_step_workspace_words(n, dim, p))
+    return fail(FV_EINVAL, "workspace needs %lld words", (long long)fv_step_workspace_words(n, dim, p));
+  if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  {
+    const char* a0 = (const char*)q_in;
+    const char* a1 = a0 + q_in_len * (int64_t)sizeof(double);
+    const char* b0 = (const char*)q_out;
+    const char* b1 = b0 + q_out_len * (int64_t)sizeof(double);
+    if (a0 < b1 && b0 < a1) return fail(FV_EINVAL, "q_in and q_out overlap");
+  }
+  fvk::CflOut co;
+  co.cfl = cfl;
+  co.dt_next = dt_next;
+  co.lambda_out = lambda_out;
+  co.ws = reinterpret_cast<unsigned long long*>(workspace);
+  rc = fvk::launch_step_gather_f64(patches, n, neighbours, q_in, q_in_len, q_out, q_out_len, dim,
+                                   p, gamma, dt_dev, max_eig, co, (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  return launched("fv_step_gather");
 }
 
 int fv_max_eigenvalue(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,

@@ -25,6 +25,30 @@ __device__ __forceinline__ T nanmax(T a, T b) {
   return (a > b || a != a) ? a : b;
 }
 
+// The same for operands that are +0, positive or NaN (wave speeds, |u|): for
+// those the IEEE bit patterns order like unsigned integers, NaN above +inf,
+// so one integer compare does it.
+__device__ __forceinline__ double nanmax_pos(double a, double b) {
+  return (unsigned long long)__double_as_longlong(a) > (unsigned long long)__double_as_longlong(b)
+             ? a
+             : b;
+}
+__device__ __forceinline__ float nanmax_pos(float a, float b) {
+  return (unsigned)__float_as_uint(a) > (unsigned)__float_as_uint(b) ? a : b;
+}
+
+// 1/x from the hardware estimate refined by two Newton steps (about 1 ulp;
+// the textbook formulas divide by rho d + 2 times, this kernel once per
+// volume).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) { return 1.0f / x; }
+
 // What a face needs from one adjacent volume besides its conserved state:
 // 1/rho, pressure and sound speed.  Computing 1/rho once per volume replaces
 // the d + 2 divisions of the textbook formulas.
@@ -36,7 +60,7 @@ struct Prim {
 template <typename T, int D>
 __device__ __forceinline__ Prim<T> decode(const T (&q)[D + 2], T gamma) {
   Prim<T> w;
-  w.ir = T(1) / q[0];
+  w.ir = recip(q[0]);
   T jj = q[1] * q[1];
 #pragma unroll
   for (int k = 1; k < D; ++k) jj = fma(q[1 + k], q[1 + k], jj);
@@ -50,7 +74,7 @@ template <typename T, int D>
 __device__ __forceinline__ T max_wave_speed(const T (&q)[D + 2], const Prim<T>& w) {
   T m = fabs(q[1]);
 #pragma unroll
-  for (int k = 1; k < D; ++k) m = nanmax(m, T(fabs(q[1 + k])));
+  for (int k = 1; k < D; ++k) m = nanmax_pos(m, T(fabs(q[1 + k])));
   return fma(m, w.ir, w.c);
 }
 
@@ -64,7 +88,7 @@ __device__ __forceinline__ void rusanov(const T (&qL)[D + 2], const Prim<T>& wL,
   constexpr int S = D + 2;
   const T uL = qL[1 + K] * wL.ir;
   const T uR = qR[1 + K] * wR.ir;
-  const T a = nanmax(T(fabs(uL)) + wL.c, T(fabs(uR)) + wR.c);
+  const T a = nanmax_pos(T(fabs(uL)) + wL.c, T(fabs(uR)) + wR.c);
   T fL[S], fR[S];
   fL[0] = qL[1 + K];
   fR[0] = qR[1 + K];

@@ -32,7 +32,7 @@ struct Geo {
   static constexpr int NEXTRA = D == 3 ? 2 * P : 1;  // in-plane faces on the high boundary
   static constexpr int NCELL = LANES + RING;         // volumes of one plane incl. its ring
   static constexpr int NV = S + 3;                   // values kept per volume: q, 1/rho, p, c
-  static constexpr int NF = D == 3 ? (P + 1) * P : P + 1;  // in-plane faces per axis and plane
+  static constexpr int NF = LANES + (D == 3 ? P : 1);  // in-plane faces per axis and plane
   static constexpr int CELLBUF = NV * NCELL;
   static constexpr int FACEBUF = (D - 1) * S * NF;
   static constexpr int SLOT = CELLBUF > FACEBUF ? CELLBUF : FACEBUF;  // LDS elements per patch
@@ -40,10 +40,48 @@ struct Geo {
   static_assert(NEXTRA <= LANES, "every high-boundary face needs its own lane");
 };
 
+// Outputs of the CFL step fused into the update (see fv_step_gather).  The
+// workspace holds (1 + groups) slot sets of kCflSlot words, each on its own
+// 256-byte line: words 0..2 = arrival count, max lambda bits, max (inf - h)
+// bits; set 0 is the top of the reduction tree, set g+1 serves group g of
+// kCflGroup consecutive workgroups.
+constexpr int kCflGroup = 64;
+constexpr int kCflSlot = 32;
+struct CflOut {
+  double cfl = 0.0;
+  double* dt_next = nullptr;
+  double* lambda_out = nullptr;
+  unsigned long long* ws = nullptr;
+};
+
+// Workgroups of the update launch and the workspace words fv_step_gather needs.
+int64_t update_workgroups(int dim, int p, int64_t n);
+inline int64_t step_workspace_words(int64_t workgroups) {
+  return (int64_t)kCflSlot * (1 + (workgroups + kCflGroup - 1) / kCflGroup);
+}
+
+// Events recorded by the dispatch of the next update launches (set through
+// fv_set_launch_events; null = not recorded).  Per calling thread.
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+LaunchEvents& launch_events();
+
 // Status for launchers: 0 ok, FV_EUNSUPPORTED when (dim, p) has no instance.
 int launch_update_f64(const fv_patch* patches, int64_t n, const double* qin, int64_t qin_len,
                       double* qout, int64_t qout_len, int out_halo, int dim, int p,
                       double gamma, const double* dt_dev, double* max_eig, hipStream_t st);
+
+int launch_update_gather_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                             const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
+                             int out_halo, int dim, int p, double gamma, const double* dt_dev,
+                             double* max_eig, hipStream_t st);
+
+int launch_step_gather_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                           const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
+                           int dim, int p, double gamma, const double* dt_dev, double* max_eig,
+                           const CflOut& cflo, hipStream_t st);
 
 int launch_patch_max_f64(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,
                          int q_halo, int which, int dim, int p, double gamma,

@@ -20,7 +20,7 @@ constexpr int kRedThreads = 256;
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = nanmax(v, T(__shfl_xor(v, o, 64)));
+  for (int o = 32; o > 0; o >>= 1) v = nanmax_pos(v, T(__shfl_xor(v, o, 64)));
   return v;
 }
 
@@ -51,7 +51,7 @@ patch_max_kernel(const fv_patch* __restrict__ patches, int64_t n, const double* 
 #pragma unroll
       for (int m = 0; m < S; ++m) qv[m] = blk[(int64_t)m * vol + idx];
       const Prim<double> wv = decode<double, D>(qv, gamma);
-      lam = nanmax(lam, max_wave_speed<double, D>(qv, wv));
+      lam = nanmax_pos(lam, max_wave_speed<double, D>(qv, wv));
     }
   }
   lam = wave_max(lam);
@@ -59,7 +59,7 @@ patch_max_kernel(const fv_patch* __restrict__ patches, int64_t n, const double* 
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 1; i < kRedThreads / 64; ++i) lam = nanmax(lam, red[i]);
+    for (int i = 1; i < kRedThreads / 64; ++i) lam = nanmax_pos(lam, red[i]);
     per_patch[b] = ok ? lam : __builtin_nan("");
   }
 }
@@ -69,10 +69,27 @@ reduce_cfl_kernel(const fv_patch* __restrict__ patches, int64_t n,
                   const double* __restrict__ per_patch, int dim, double cfl,
                   double* __restrict__ lambda_out, double* __restrict__ dt_out) {
   __shared__ double rl[16], rh[16];
+  constexpr int U = 4;  // patches per thread and round: their loads are issued together
   double lam = 0.0, h = __builtin_inf();
-  for (int64_t b = threadIdx.x; b < n; b += blockDim.x) {
-    lam = nanmax(lam, per_patch[b]);
-    for (int j = 0; j < dim; ++j) h = fmin(h, patches[b].dx[j]);
+  for (int64_t b0 = threadIdx.x; b0 < n; b0 += (int64_t)U * blockDim.x) {
+    double lv[U], hv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t b = b0 + (int64_t)u * blockDim.x;
+      lv[u] = 0.0;
+      hv[u] = __builtin_inf();
+      if (b < n) {
+        lv[u] = per_patch[b];
+        const double* dx = patches[b].dx;
+        hv[u] = fmin(dx[0], dx[1]);
+        if (dim == 3) hv[u] = fmin(hv[u], dx[2]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      lam = nanmax_pos(lam, lv[u]);
+      h = fmin(h, hv[u]);
+    }
   }
   lam = wave_max(lam);
 #pragma unroll
@@ -84,7 +101,7 @@ reduce_cfl_kernel(const fv_patch* __restrict__ patches, int64_t n,
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
-      lam = nanmax(lam, rl[i]);
+      lam = nanmax_pos(lam, rl[i]);
       h = fmin(h, rh[i]);
     }
     if (lambda_out) *lambda_out = lam;

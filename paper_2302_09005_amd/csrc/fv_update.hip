@@ -11,8 +11,8 @@
 //
 // Per plane:
 //   A. each lane publishes its volume (q, 1/rho, p, c) to LDS; lanes
-//      l < RING also load, decode and publish one face-halo volume of the
-//      plane ("ring"), so halo volumes are decoded once;
+//      l < RING also publish one face-halo volume of the plane ("ring"), so
+//      halo volumes are decoded once;
 //   B. each lane computes the in-plane faces on its low side; lanes
 //      l < NEXTRA compute the faces on the patch's high boundary;
 //   C. the face fluxes go to LDS (the plane buffer is reused);
@@ -25,8 +25,19 @@
 // volume and ring loads are issued one plane ahead, before the LDS phases,
 // so HBM latency overlaps the arithmetic of the current plane.
 //
+// Two sources for the face halo, one kernel body:
+//   * HALO (the paper's interface): every patch block carries its own halo
+//     layer, [s][(P+2)^D]; the halo is read from the block itself.
+//   * GATHER: blocks are compact, [s][P^D], and each face-halo volume is read
+//     directly from the facing interior volume of the neighbouring patch (or,
+//     at a transmissive boundary, from the patch's own boundary volume).  This
+//     fuses the halo exchange into the tile gather: the multi-step loop needs
+//     no separate halo-fill pass and no halo storage.  Results are identical.
+//
 // The per-patch maximum is reduced across the patch's lanes with wave
 // shuffles (and LDS across waves when a patch spans several waves).
+#include <hip/hip_ext.h>
+
 #include "fv_euler.hpp"
 #include "fv_internal.hpp"
 
@@ -34,12 +45,18 @@ namespace fvk {
 
 namespace {
 
-template <typename T, int D, int P>
+// IEEE bit pattern of +inf: for positive doubles, kInfBits - bits(h) is
+// positive and decreases as h grows, so an integer max of it is a min of h.
+constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
+
+template <typename T, int D, int P, bool GATHER, bool CFL>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, Geo<D, P>::NT)))
 fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
+                 const int64_t* __restrict__ neighbours,
                  const T* __restrict__ qin, int64_t qin_len,
                  T* __restrict__ qout, int64_t qout_len, int out_halo, T gamma,
-                 const double* __restrict__ dt_dev, double* __restrict__ max_eig) {
+                 const double* __restrict__ dt_dev, double* __restrict__ max_eig,
+                 CflOut cflo) {
   using G = Geo<D, P>;
   constexpr int S = G::S;
   constexpr int K = D - 1;  // marching axis
@@ -47,56 +64,125 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   constexpr int LANES = G::LANES;
   constexpr int NCELL = G::NCELL;
   constexpr int NF = G::NF;
+  // strides of the input blocks: component, marching-axis plane
+  constexpr int CS = GATHER ? G::VOUT : G::VIN;
+  constexpr int PS = GATHER ? G::SMO : G::SM;
 
   __shared__ T lds[G::PPW * G::SLOT];
   __shared__ T red[G::NT / 64];
 
   const int tid = threadIdx.x;
-  const int slot = tid / LANES;
-  const int l = tid - slot * LANES;
+  const int slot = G::PPW == 1 ? 0 : tid / LANES;
+  const int l = G::PPW == 1 ? tid : tid - slot * LANES;
   const int64_t b = (int64_t)blockIdx.x * G::PPW + slot;
-  const bool in_range = (slot < G::PPW) && (b < n);
+  const bool in_range = (G::PPW == 1 || slot < G::PPW) && (b < n);
   const int x = l % P;
   const int y = (D == 3) ? l / P : 0;
+  const bool has_ring = l < G::RING;
+  // ring volume of this lane: quadrant (= the face it lies across) and
+  // position along it
+  const int q4 = D == 3 ? l / P : l;
+  const int rr = D == 3 ? l - q4 * P : 0;
 
-  // ---- descriptor and device-side bounds check --------------------------
+  // ---- descriptor, sources, device-side bounds checks -------------------
+  const int64_t blk_in = (int64_t)S * (GATHER ? G::VOUT : G::VIN);
+  const int64_t blk_out = out_halo ? (int64_t)S * G::VIN : (int64_t)S * G::VOUT;
   int64_t off_in = 0, off_out = 0;
+  int64_t lo_base = 0, hi_base = 0, ring_src = 0;  // element offsets (GATHER)
   T r[3] = {T(0), T(0), T(0)};
+  double hmin = __builtin_inf();
   bool ok = false;
   if (in_range) {
     const fv_patch pd = patches[b];
     off_in = pd.q_in;
     off_out = pd.q_out;
-    const int64_t blk_in = (int64_t)S * G::VIN;
-    const int64_t blk_out = out_halo ? (int64_t)S * G::VIN : (int64_t)S * G::VOUT;
     ok = pd.p == P && off_in >= 0 && off_in <= qin_len - blk_in && off_out >= 0 &&
          off_out <= qout_len - blk_out;
     const double dt = dt_dev ? *dt_dev : pd.dt;
 #pragma unroll
     for (int j = 0; j < D; ++j) r[j] = T(dt / pd.dx[j]);
+    hmin = pd.dx[0];
+#pragma unroll
+    for (int j = 1; j < D; ++j) hmin = fmin(hmin, pd.dx[j]);
+    if constexpr (GATHER) {
+      // face order -x, +x, -y, +y[, -z, +z]; -1 = transmissive
+      int64_t nbo[2 * D];
+#pragma unroll
+      for (int f = 0; f < 2 * D; ++f) {
+        const int64_t nb = neighbours[b * 2 * D + f];
+        nbo[f] = -1;
+        if (nb >= 0 && nb < n) {
+          const fv_patch& pn = patches[nb];
+          if (pn.p == P && pn.q_in >= 0 && pn.q_in <= qin_len - blk_in) nbo[f] = pn.q_in;
+          else ok = false;
+        } else if (nb != -1) {
+          ok = false;
+        }
+      }
+      constexpr int fl = 2 * K, fh = 2 * K + 1;  // marching-axis faces
+      constexpr int last = (P - 1) * G::SMO;
+      // block bases of the two marching-axis halo planes (plane offset included)
+      lo_base = nbo[fl] >= 0 ? nbo[fl] + last : off_in;
+      hi_base = nbo[fh] >= 0 ? nbo[fh] : off_in + last;
+      if (has_ring) {
+        // the facing volume of the neighbour, or the own boundary volume
+        const bool hasnb = nbo[q4] >= 0;
+        int idx;
+        if (D == 3) {
+          idx = q4 == 0 ? (hasnb ? P - 1 : 0) + P * rr
+              : q4 == 1 ? (hasnb ? 0 : P - 1) + P * rr
+              : q4 == 2 ? rr + P * (hasnb ? P - 1 : 0)
+                        : rr + P * (hasnb ? 0 : P - 1);
+        } else {
+          idx = q4 == 0 ? (hasnb ? P - 1 : 0) : (hasnb ? 0 : P - 1);
+        }
+        ring_src = (hasnb ? nbo[q4] : off_in) + idx;
+      }
+    }
   }
   T* cell = lds + (ok ? slot * G::SLOT : 0);  // plane buffer [NV][NCELL]
-  T* face = cell;                             // face buffer [D-1][S][NF], same storage
+  T* face = cell;                             // face buffers, same storage
 
-  // own column (halo'd in-plane index), ring volume, output column
-  const int in_col = (x + 1) + (D == 3 ? (y + 1) * W : 0);
-  const bool has_ring = l < G::RING;
-  int ring_col = 0;
+  // in-plane element index of the own column (compact and halo'd) and of
+  // the ring volume inside the own halo'd block
+  const int col_c = x + (D == 3 ? y * P : 0);
+  const int col_h = (x + 1) + (D == 3 ? (y + 1) * W : 0);
+  int ring_h;
   if (D == 3) {
-    const int q4 = l / P, rr = l - q4 * P;
-    ring_col = q4 == 0 ? (rr + 1) * W
-             : q4 == 1 ? (P + 1) + (rr + 1) * W
-             : q4 == 2 ? (rr + 1)
-                       : (rr + 1) + (P + 1) * W;
+    ring_h = q4 == 0 ? (rr + 1) * W
+           : q4 == 1 ? (P + 1) + (rr + 1) * W
+           : q4 == 2 ? (rr + 1)
+                     : (rr + 1) + (P + 1) * W;
   } else {
-    ring_col = l == 0 ? 0 : P + 1;
+    ring_h = l == 0 ? 0 : P + 1;
   }
-  const T* col = qin + off_in + in_col;
-  const T* ring = qin + off_in + ring_col;
+  const int col_in = GATHER ? col_c : col_h;
+  const int col_out = out_halo ? col_h + G::SM : col_c;
   const int64_t ostride = out_halo ? G::SM : G::SMO;
   const int64_t ocomp = out_halo ? G::VIN : G::VOUT;
-  T* outp = qout + off_out +
-            (out_halo ? (int64_t)in_col + G::SM : (int64_t)x + (D == 3 ? y * P : 0));
+
+  const T* gin = qin + off_in + col_in;
+  const T* glo = qin + lo_base + col_c;
+  const T* ghi = qin + hi_base + col_c;
+  const T* gring = GATHER ? qin + ring_src : qin + off_in + ring_h;
+  T* gout = qout + off_out + col_out;
+
+  // unknown m of the own column at marching-axis storage plane j in [0, P+1]
+  // (0 and P+1 are the halo planes)
+  auto ld_own = [&](int j, int m) -> T {
+    if constexpr (GATHER) {
+      if (j == 0) return glo[(int64_t)m * CS];
+      if (j == P + 1) return ghi[(int64_t)m * CS];
+      return gin[(int64_t)m * CS + (int64_t)(j - 1) * PS];
+    } else {
+      return gin[(int64_t)m * CS + (int64_t)j * PS];
+    }
+  };
+  // unknown m of the ring volume at interior plane j in [1, P]
+  auto ld_ring = [&](int j, int m) -> T {
+    return gring[(int64_t)m * CS + (int64_t)(GATHER ? j - 1 : j) * PS];
+  };
+  auto st_out = [&](int pl, int m, T v) { gout[(int64_t)m * ocomp + (int64_t)pl * ostride] = v; };
 
   // ---- prologue: planes -1 and 0, first marching-axis face ---------------
   T qlo[S], qc[S], qnx[S], rraw[S];
@@ -107,13 +193,15 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
     qnx[m] = T(1);
     rraw[m] = T(1);
   }
-  if (ok) {
+  // a patch that failed its checks skips all work (its max_eig becomes NaN)
+  const bool act = ok;
+  if (act) {
 #pragma unroll
     for (int m = 0; m < S; ++m) {
-      qlo[m] = col[(int64_t)m * G::VIN];
-      qc[m] = col[(int64_t)m * G::VIN + G::SM];
-      qnx[m] = col[(int64_t)m * G::VIN + 2 * G::SM];
-      if (has_ring) rraw[m] = ring[(int64_t)m * G::VIN + G::SM];
+      qlo[m] = ld_own(0, m);
+      qc[m] = ld_own(1, m);
+      qnx[m] = ld_own(2, m);
+      if (has_ring) rraw[m] = ld_ring(1, m);
     }
   }
   Prim<T> wc = decode<T, D>(qc, gamma);
@@ -124,27 +212,39 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   }
   T lam = T(0);
 
+  // face buffers: x-faces [y][x] for the low face of every volume followed by
+  // the high-boundary faces [y]; y-faces [y][x] for y in [0, P] (the last row
+  // is the high boundary).  Every lane's low and high faces then sit at
+  // consecutive addresses across lanes (no LDS bank conflicts).
+  constexpr int FX_EXTRA = LANES;
+  const int fx_lo = l;
+  const int fx_hi = x < P - 1 ? l + 1 : FX_EXTRA + (D == 3 ? y : 0);
+  const int fy_lo = l;
+  const int fy_hi = l + P;
+
+  // fully unrolled for small patches so that the rolling registers are
+  // renamed instead of copied
+  constexpr int UNROLL = P <= 8 ? P : 2;
+#pragma unroll UNROLL
   for (int pl = 0; pl < P; ++pl) {
-    // prefetch: ring of plane pl+1 and own volume of plane pl+2
     T rnext[S], qnn[S];
 #pragma unroll
     for (int m = 0; m < S; ++m) {
       rnext[m] = rraw[m];
       qnn[m] = qnx[m];
     }
-    if (ok) {
+    if (act) {
       if (has_ring && pl + 1 < P) {
 #pragma unroll
-        for (int m = 0; m < S; ++m) rnext[m] = ring[(int64_t)m * G::VIN + (int64_t)(pl + 2) * G::SM];
+        for (int m = 0; m < S; ++m) rnext[m] = ld_ring(pl + 2, m);
       }
       if (pl + 3 <= P + 1) {
 #pragma unroll
-        for (int m = 0; m < S; ++m) qnn[m] = col[(int64_t)m * G::VIN + (int64_t)(pl + 3) * G::SM];
+        for (int m = 0; m < S; ++m) qnn[m] = ld_own(pl + 3, m);
       }
     }
-
     // A. publish own and ring volumes of this plane
-    if (ok) {
+    if (act) {
 #pragma unroll
       for (int m = 0; m < S; ++m) cell[m * NCELL + l] = qc[m];
       cell[(S + 0) * NCELL + l] = wc.ir;
@@ -163,7 +263,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
 
     // B. in-plane faces on the low side of each volume, plus the high boundary
     T Fl0[S], Fl1[S], Fx[S];
-    if (ok) {
+    if (act) {
       {
         const int nb = x > 0 ? l - 1 : LANES + (D == 3 ? y : 0);
         T qn[S];
@@ -207,31 +307,34 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
     }
     __syncthreads();
 
-    // C. publish face fluxes: face[k][m][line * (P+1) + position along k]
-    if (ok) {
+    // C. publish face fluxes: face[k][m][index]
+    if (act) {
 #pragma unroll
-      for (int m = 0; m < S; ++m) face[m * NF + y * (P + 1) + x] = Fl0[m];
+      for (int m = 0; m < S; ++m) face[m * NF + fx_lo] = Fl0[m];
       if constexpr (D == 3) {
 #pragma unroll
-        for (int m = 0; m < S; ++m) face[(S + m) * NF + x * (P + 1) + y] = Fl1[m];
+        for (int m = 0; m < S; ++m) face[(S + m) * NF + fy_lo] = Fl1[m];
       }
       if (l < G::NEXTRA) {
         const bool ydir = (D == 3) && l >= P;
         const int t = ydir ? l - P : l;
-        const int base = (ydir ? S * NF : 0) + t * (P + 1) + P;
+        const int base = ydir ? S * NF + P * P + t : FX_EXTRA + t;
 #pragma unroll
         for (int m = 0; m < S; ++m) face[base + m * NF] = Fx[m];
       }
     }
     __syncthreads();
 
-    // D. high-side faces, marching-axis face, update, store, running maximum
-    if (ok) {
+    // D. high-side faces, marching-axis face, update, store, running maximum.
+    // The ring of the next plane is requested first (its registers were freed
+    // in A) and the own column two planes ahead last (its registers are freed
+    // here), so one copy of each is in flight across the iteration.
+    if (act) {
       T Fr0[S], Fr1[S];
 #pragma unroll
       for (int m = 0; m < S; ++m) {
-        Fr0[m] = face[m * NF + y * (P + 1) + x + 1];
-        if constexpr (D == 3) Fr1[m] = face[(S + m) * NF + x * (P + 1) + y + 1];
+        Fr0[m] = face[m * NF + fx_hi];
+        if constexpr (D == 3) Fr1[m] = face[(S + m) * NF + fy_hi];
       }
       const Prim<T> wu = decode<T, D>(qnx, gamma);
       T Fhi[S];
@@ -242,10 +345,10 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
         T v = fma(-r[0], Fr0[m] - Fl0[m], qc[m]);
         if constexpr (D == 3) v = fma(-r[1], Fr1[m] - Fl1[m], v);
         qn[m] = fma(-r[K], Fhi[m] - Flo[m], v);
-        outp[(int64_t)m * ocomp + (int64_t)pl * ostride] = qn[m];
+        st_out(pl, m, qn[m]);
       }
       const Prim<T> wn = decode<T, D>(qn, gamma);
-      lam = nanmax(lam, max_wave_speed<T, D>(qn, wn));
+      lam = nanmax_pos(lam, max_wave_speed<T, D>(qn, wn));
 #pragma unroll
       for (int m = 0; m < S; ++m) {
         qc[m] = qnx[m];
@@ -266,13 +369,13 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   if constexpr (pow2) {
     constexpr int seg = LANES < 64 ? LANES : 64;
 #pragma unroll
-    for (int o = seg / 2; o > 0; o >>= 1) lam = nanmax(lam, T(__shfl_xor(lam, o, 64)));
+    for (int o = seg / 2; o > 0; o >>= 1) lam = nanmax_pos(lam, T(__shfl_xor(lam, o, 64)));
     if constexpr (LANES > 64) {
       if ((tid & 63) == 0) red[tid >> 6] = lam;
       __syncthreads();
       if (tid == 0) {
 #pragma unroll
-        for (int w = 1; w < LANES / 64; ++w) lam = nanmax(lam, red[w]);
+        for (int w = 1; w < LANES / 64; ++w) lam = nanmax_pos(lam, red[w]);
       }
     }
   } else {
@@ -280,42 +383,107 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
     lds[tid < G::PPW * G::SLOT ? tid : 0] = lam;
     __syncthreads();
     if (in_range && l == 0) {
-      for (int i = 1; i < LANES; ++i) lam = nanmax(lam, lds[slot * LANES + i]);
+      for (int i = 1; i < LANES; ++i) lam = nanmax_pos(lam, lds[slot * LANES + i]);
     }
   }
-  if (in_range && l == 0 && max_eig) {
-    max_eig[b] = ok ? double(lam) : __builtin_nan("");
+  const double lam_b = ok ? double(lam) : __builtin_nan("");
+  if (in_range && l == 0 && max_eig) max_eig[b] = lam_b;
+
+  if constexpr (CFL) {
+    // Fused CFL step.  Patch maxima and smallest volume widths are folded
+    // with device-scope atomic maxima of IEEE bit patterns (values >= 0 or
+    // NaN, so integer order is numeric order with NaN on top, and the result
+    // does not depend on the order of arrival).  Same-address atomics
+    // serialize, so the fold is a two-level tree: the workgroups of a group
+    // (kCflGroup consecutive ones) fold into the group's slots, the last to
+    // arrive folds the group's totals into the top slots, and the last group
+    // to arrive computes the next time step.  Every slot is cleared by the
+    // workgroup that consumed it.  Ordering without fences: the maxima are
+    // returning atomics whose results feed the arrival increment, so a fold
+    // is counted only after it has been performed.
+    __shared__ unsigned long long dep_s[G::PPW];
+    __shared__ int stage;  // 1: last of its group, 2: last group overall
+    const unsigned nwg = gridDim.x;
+    const unsigned grp = blockIdx.x / kCflGroup;
+    const unsigned ngrp = (nwg + kCflGroup - 1) / kCflGroup;
+    const unsigned gsize = min((unsigned)kCflGroup, nwg - grp * kCflGroup);
+    unsigned long long* gs = cflo.ws + (size_t)kCflSlot * (grp + 1);  // group slots
+    unsigned long long* ts = cflo.ws;                                 // top slots
+    if (in_range && l == 0) {
+      const unsigned long long o1 = __hip_atomic_fetch_max(
+          &gs[1], (unsigned long long)__double_as_longlong(lam_b), __ATOMIC_RELAXED,
+          __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long o2 = __hip_atomic_fetch_max(
+          &gs[2], kInfBits - (unsigned long long)__double_as_longlong(hmin),
+          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // never true (no maximum reaches all ones); it only ties the arrival
+      // below to the two results above
+      dep_s[slot] = (o1 == ~0ull || o2 == ~0ull) ? 1ull : 0ull;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long dep = 0;
+#pragma unroll
+      for (int i = 0; i < G::PPW; ++i)
+        if ((int64_t)blockIdx.x * G::PPW + i < n) dep |= dep_s[i];
+      const unsigned long long before =
+          __hip_atomic_fetch_add(&gs[0], 1ull + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      stage = before == gsize - 1 ? 1 : 0;
+      if (stage) {
+        // last of the group: move the group's totals to the top
+        const unsigned long long lb =
+            __hip_atomic_exchange(&gs[1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long hb =
+            __hip_atomic_exchange(&gs[2], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_exchange(&gs[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long t1 =
+            __hip_atomic_fetch_max(&ts[1], lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long t2 =
+            __hip_atomic_fetch_max(&ts[2], hb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long tdep = (t1 == ~0ull || t2 == ~0ull) ? 1ull : 0ull;
+        const unsigned long long tb =
+            __hip_atomic_fetch_add(&ts[0], 1ull + tdep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tb == ngrp - 1) {
+          const unsigned long long Lb =
+              __hip_atomic_exchange(&ts[1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const unsigned long long Hb =
+              __hip_atomic_exchange(&ts[2], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_exchange(&ts[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const double L = __longlong_as_double((long long)Lb);
+          const double h = __longlong_as_double((long long)(kInfBits - Hb));
+          *cflo.dt_next = cflo.cfl * h / ((double)D * L);
+          if (cflo.lambda_out) *cflo.lambda_out = L;
+        }
+      }
+    }
   }
 }
 
-template <typename T, int D, int P>
-int launch(const fv_patch* patches, int64_t n, const T* qin, int64_t qin_len, T* qout,
-           int64_t qout_len, int out_halo, T gamma, const double* dt_dev, double* max_eig,
-           hipStream_t st) {
+template <typename T, int D, int P, bool GATHER, bool CFL>
+int launch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin, int64_t qin_len,
+           T* qout, int64_t qout_len, int out_halo, T gamma, const double* dt_dev,
+           double* max_eig, const CflOut& cflo, hipStream_t st) {
   using G = Geo<D, P>;
   static_assert(G::PPW * G::LANES <= G::NT, "workgroup too small");
-  static_assert(G::LANES % G::PPW == 0 || G::LANES < 64, "bad packing");
   const int64_t blocks = (n + G::PPW - 1) / G::PPW;
-  hipLaunchKernelGGL((fv_update_kernel<T, D, P>), dim3((unsigned)blocks), dim3(G::NT), 0, st,
-                     patches, n, qin, qin_len, qout, qout_len, out_halo, gamma, dt_dev, max_eig);
+  const LaunchEvents& ev = launch_events();
+  // with caller events the dispatch packet itself records them, so they time
+  // the kernel's execution and nothing around it
+  hipExtLaunchKernelGGL((fv_update_kernel<T, D, P, GATHER, CFL>), dim3((unsigned)blocks),
+                        dim3(G::NT), 0, st, ev.start, ev.stop, 0, patches, n, nbr, qin, qin_len,
+                        qout, qout_len, out_halo, gamma, dt_dev, max_eig, cflo);
   return 0;
 }
 
-}  // namespace
-
-bool update_supported(int dim, int p) {
-  if (dim == 2) return p == 4 || p == 8 || p == 16 || p == 17 || p == 32;
-  if (dim == 3) return p == 4 || p == 8 || p == 16;
-  return false;
-}
-
-int launch_update_f64(const fv_patch* patches, int64_t n, const double* qin, int64_t qin_len,
-                      double* qout, int64_t qout_len, int out_halo, int dim, int p,
-                      double gamma, const double* dt_dev, double* max_eig, hipStream_t st) {
-#define FV_CASE(DD, PP)                                                                   \
-  if (dim == DD && p == PP)                                                               \
-    return launch<double, DD, PP>(patches, n, qin, qin_len, qout, qout_len, out_halo, gamma, \
-                                  dt_dev, max_eig, st);
+template <bool GATHER, bool CFL>
+int dispatch(const fv_patch* patches, int64_t n, const int64_t* nbr, const double* qin,
+             int64_t qin_len, double* qout, int64_t qout_len, int out_halo, int dim, int p,
+             double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
+             hipStream_t st) {
+#define FV_CASE(DD, PP)                                                                     \
+  if (dim == DD && p == PP)                                                                 \
+    return launch<double, DD, PP, GATHER, CFL>(patches, n, nbr, qin, qin_len, qout, qout_len, \
+                                               out_halo, gamma, dt_dev, max_eig, cflo, st);
   FV_CASE(2, 4)
   FV_CASE(2, 8)
   FV_CASE(2, 16)
@@ -326,6 +494,52 @@ int launch_update_f64(const fv_patch* patches, int64_t n, const double* qin, int
   FV_CASE(3, 16)
 #undef FV_CASE
   return FV_EUNSUPPORTED;
+}
+
+}  // namespace
+
+int64_t update_workgroups(int dim, int p, int64_t n) {
+#define FV_CASE(DD, PP) \
+  if (dim == DD && p == PP) return (n + Geo<DD, PP>::PPW - 1) / Geo<DD, PP>::PPW;
+  FV_CASE(2, 4)
+  FV_CASE(2, 8)
+  FV_CASE(2, 16)
+  FV_CASE(2, 17)
+  FV_CASE(2, 32)
+  FV_CASE(3, 4)
+  FV_CASE(3, 8)
+  FV_CASE(3, 16)
+#undef FV_CASE
+  return 0;
+}
+
+bool update_supported(int dim, int p) {
+  if (dim == 2) return p == 4 || p == 8 || p == 16 || p == 17 || p == 32;
+  if (dim == 3) return p == 4 || p == 8 || p == 16;
+  return false;
+}
+
+int launch_update_f64(const fv_patch* patches, int64_t n, const double* qin, int64_t qin_len,
+                      double* qout, int64_t qout_len, int out_halo, int dim, int p,
+                      double gamma, const double* dt_dev, double* max_eig, hipStream_t st) {
+  return dispatch<false, false>(patches, n, nullptr, qin, qin_len, qout, qout_len, out_halo, dim,
+                                p, gamma, dt_dev, max_eig, CflOut{}, st);
+}
+
+int launch_update_gather_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                             const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
+                             int out_halo, int dim, int p, double gamma, const double* dt_dev,
+                             double* max_eig, hipStream_t st) {
+  return dispatch<true, false>(patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo,
+                               dim, p, gamma, dt_dev, max_eig, CflOut{}, st);
+}
+
+int launch_step_gather_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                           const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
+                           int dim, int p, double gamma, const double* dt_dev, double* max_eig,
+                           const CflOut& cflo, hipStream_t st) {
+  return dispatch<true, true>(patches, n, neighbours, qin, qin_len, qout, qout_len, 0, dim, p,
+                              gamma, dt_dev, max_eig, cflo, st);
 }
 
 }  // namespace fvk

@@ -54,11 +54,21 @@ def library():
     lib.fv_abi_version.restype = i32
     lib.fv_supported.argtypes = [i32, i32]
     lib.fv_supported.restype = i32
-    lib.fv_check_patches.argtypes = [vp, i64, i32, i32, i32, i64, i64]
+    lib.fv_set_launch_events.argtypes = [vp, vp]
+    lib.fv_set_launch_events.restype = i32
+    lib.fv_check_patches.argtypes = [vp, i64, i32, i32, i32, i32, i64, i64]
     lib.fv_check_patches.restype = i32
     lib.fv_batch_update.argtypes = [vp, i64, vp, i64, vp, i64, i32, i32, i32, i32, i32, f64,
                                     vp, vp, vp]
     lib.fv_batch_update.restype = i32
+    lib.fv_batch_update_gather.argtypes = [vp, i64, vp, vp, i64, vp, i64, i32, i32, i32, i32,
+                                           f64, vp, vp, vp]
+    lib.fv_batch_update_gather.restype = i32
+    lib.fv_step_gather.argtypes = [vp, i64, vp, vp, i64, vp, i64, i32, i32, i32, f64, f64, vp, vp,
+                                   vp, vp, vp, i64, vp]
+    lib.fv_step_gather.restype = i32
+    lib.fv_step_workspace_words.argtypes = [i64, i32, i32]
+    lib.fv_step_workspace_words.restype = i64
     lib.fv_max_eigenvalue.argtypes = [vp, i64, vp, i64, i32, i32, i32, i32, i32, f64, vp, vp, vp]
     lib.fv_max_eigenvalue.restype = i32
     lib.fv_cfl_timestep.argtypes = [vp, i64, vp, i32, f64, vp, vp, vp]
@@ -99,6 +109,12 @@ def _n_patches(patches):
     return nbytes // PATCH_DTYPE.itemsize
 
 
+def set_launch_events(start=None, stop=None):
+    """fv_set_launch_events: raw hipEvent_t handles (ints) recorded by the
+    dispatch of the following update launches; None, None to stop."""
+    _check(library().fv_set_launch_events(start, stop))
+
+
 def abi_version():
     return library().fv_abi_version()
 
@@ -107,16 +123,16 @@ def supported(dim, p):
     return bool(library().fv_supported(dim, p))
 
 
-def check_patches(desc, dim, p, q_out_halo, q_in_len, q_out_len):
+def check_patches(desc, dim, p, q_out_halo, q_in_len, q_out_len, q_in_halo=True):
     """Validate a host descriptor array (numpy, PATCH_DTYPE) with fv_check_patches."""
     desc = np.ascontiguousarray(desc, dtype=PATCH_DTYPE)
     _check(library().fv_check_patches(desc.ctypes.data_as(ctypes.c_void_p), desc.shape[0],
-                                      dim, p, int(bool(q_out_halo)), int(q_in_len),
-                                      int(q_out_len)))
+                                      dim, p, int(bool(q_in_halo)), int(bool(q_out_halo)),
+                                      int(q_in_len), int(q_out_len)))
 
 
 def upload_patches(desc, device="cuda", *, dim=None, p=None, q_out_halo=None, q_in_len=None,
-                   q_out_len=None):
+                   q_out_len=None, q_in_halo=True):
     """Copy a host descriptor array to the device (as a uint8 tensor).
 
     When dim/p/lengths are given the array is validated first with
@@ -125,7 +141,7 @@ def upload_patches(desc, device="cuda", *, dim=None, p=None, q_out_halo=None, q_
     import torch
     desc = np.ascontiguousarray(desc, dtype=PATCH_DTYPE)
     if dim is not None:
-        check_patches(desc, dim, p, q_out_halo, q_in_len, q_out_len)
+        check_patches(desc, dim, p, q_out_halo, q_in_len, q_out_len, q_in_halo)
     raw = torch.from_numpy(desc.view(np.uint8).reshape(-1).copy())
     return raw.to(device)
 
@@ -145,6 +161,66 @@ def batch_update(patches, q_in, q_out, *, dim, p, gamma=1.4, q_out_halo=True, dt
     _check(library().fv_batch_update(_ptr(patches), n, _ptr(q_in), q_in.numel(), _ptr(q_out),
                                      q_out.numel(), int(bool(q_out_halo)), dim, p, 1, dim + 2,
                                      float(gamma), _ptr(dt), _ptr(max_eig), _stream(stream)))
+
+
+def _dev_nbr(neighbours, n, dim):
+    import torch
+    if not (isinstance(neighbours, torch.Tensor) and neighbours.is_cuda
+            and neighbours.dtype == torch.int64 and neighbours.is_contiguous()
+            and neighbours.numel() == 2 * dim * n):
+        raise TypeError("neighbours must be a contiguous int64 device tensor [n, 2*dim]")
+    return neighbours
+
+
+def batch_update_gather(patches, neighbours, q_in, q_out, *, dim, p, gamma=1.4,
+                        q_out_halo=False, dt=None, max_eig=None, stream=None):
+    """fv_batch_update_gather: update with the face-halo exchange fused into the gather."""
+    _dev_f64(q_in, "q_in")
+    _dev_f64(q_out, "q_out")
+    if max_eig is not None:
+        _dev_f64(max_eig, "max_eig")
+    if dt is not None:
+        _dev_f64(dt, "dt")
+    n = _n_patches(patches)
+    _dev_nbr(neighbours, n, dim)
+    if max_eig is not None and max_eig.numel() < n:
+        raise ValueError("max_eig needs one entry per patch")
+    _check(library().fv_batch_update_gather(_ptr(patches), n, _ptr(neighbours), _ptr(q_in),
+                                            q_in.numel(), _ptr(q_out), q_out.numel(),
+                                            int(bool(q_out_halo)), dim, p, dim + 2, float(gamma),
+                                            _ptr(dt), _ptr(max_eig), _stream(stream)))
+
+
+def step_workspace_words(n, dim, p):
+    """Words of the zero-initialised int64 workspace fv_step_gather needs."""
+    return int(library().fv_step_workspace_words(n, dim, p))
+
+
+def step_gather(patches, neighbours, q_in, q_out, dt, dt_next, workspace, *, dim, p, gamma=1.4,
+                cfl=0.4, max_eig=None, lambda_out=None, stream=None):
+    """fv_step_gather: update (halo exchange fused) + next CFL time step, one launch."""
+    import torch
+    _dev_f64(q_in, "q_in")
+    _dev_f64(q_out, "q_out")
+    _dev_f64(dt, "dt")
+    _dev_f64(dt_next, "dt_next")
+    for t, name in ((max_eig, "max_eig"), (lambda_out, "lambda_out")):
+        if t is not None:
+            _dev_f64(t, name)
+    n = _n_patches(patches)
+    need = step_workspace_words(n, dim, p)
+    if not (workspace.is_cuda and workspace.dtype in (torch.int64, torch.uint64)
+            and workspace.numel() >= need and workspace.is_contiguous()):
+        raise TypeError(f"workspace must be a contiguous 64-bit integer device tensor of "
+                        f">= {need} words")
+    _dev_nbr(neighbours, n, dim)
+    if max_eig is not None and max_eig.numel() < n:
+        raise ValueError("max_eig needs one entry per patch")
+    _check(library().fv_step_gather(_ptr(patches), n, _ptr(neighbours), _ptr(q_in), q_in.numel(),
+                                    _ptr(q_out), q_out.numel(), dim, p, dim + 2, float(gamma),
+                                    float(cfl), _ptr(dt), _ptr(max_eig), _ptr(dt_next),
+                                    _ptr(lambda_out), _ptr(workspace), workspace.numel(),
+                                    _stream(stream)))
 
 
 def max_eigenvalue(patches, q, per_patch, global_out=None, *, dim, p, gamma=1.4, q_halo=True,
@@ -176,49 +252,98 @@ def cfl_timestep(patches, per_patch, *, dim, cfl=0.4, lambda_out=None, dt_out=No
 
 def fill_halo(patches, neighbours, q, *, dim, p, which=FV_OFFSETS_IN, stream=None):
     """fv_fill_halo: face-halo exchange in place (neighbour -1 = transmissive)."""
-    import torch
     _dev_f64(q, "q")
     n = _n_patches(patches)
-    if not (neighbours.is_cuda and neighbours.dtype == torch.int64 and neighbours.is_contiguous()
-            and neighbours.numel() == 2 * dim * n):
-        raise TypeError("neighbours must be a contiguous int64 device tensor [n, 2*dim]")
+    _dev_nbr(neighbours, n, dim)
     _check(library().fv_fill_halo(_ptr(patches), n, _ptr(neighbours), _ptr(q), q.numel(), which,
                                   dim, p, 1, dim + 2, _stream(stream)))
 
 
 class Stepper:
-    """Device-resident multi-step driver over one patch batch (halo'd ping-pong).
+    """Device-resident multi-step driver over one patch batch (ping-pong buffers).
 
-    Each step: dt from the current per-patch maxima (fv_cfl_timestep), update
-    into the other buffer (fv_batch_update, which also yields the next per-patch
-    maxima), face-halo fill (fv_fill_halo), swap.  Nothing leaves the device.
+    mode "fused" (default): compact blocks [s][p^d]; each step is ONE launch of
+    fv_step_gather (update with the halo exchange fused into the gather, plus
+    the next step's CFL time step).  mode "gather": the same arithmetic as two
+    launches, fv_cfl_timestep + fv_batch_update_gather.  mode "halo": blocks
+    with halo [s][(p+2)^d]; fv_cfl_timestep + fv_batch_update + fv_fill_halo
+    (the paper's interface, halo kept consistent by a separate pass).  The time
+    step always comes from the per-patch maxima of the previous step's state;
+    nothing leaves the device.  q0 must be laid out for the mode
+    (workloads.PatchGrid.pack for "halo", pack_compact otherwise).
     """
 
-    def __init__(self, desc, neighbours, q0, *, dim, p, gamma=1.4, cfl=0.4, device="cuda"):
+    def __init__(self, desc, neighbours, q0, *, dim, p, gamma=1.4, cfl=0.4, mode="fused",
+                 device="cuda"):
         import torch
+        if mode not in ("fused", "gather", "halo"):
+            raise ValueError("mode must be 'fused', 'gather' or 'halo'")
         desc = np.ascontiguousarray(desc, dtype=PATCH_DTYPE)
         if not np.array_equal(desc["q_in"], desc["q_out"]):
             raise ValueError("the ping-pong stepper needs q_in == q_out offsets")
         q0 = np.ascontiguousarray(q0, dtype=np.float64)
+        self.mode = mode
+        self.halo = mode == "halo"
         self.dim, self.p, self.gamma, self.cfl = dim, p, gamma, cfl
         self.n = desc.shape[0]
-        self.patches = upload_patches(desc, device, dim=dim, p=p, q_out_halo=True,
-                                      q_in_len=q0.size, q_out_len=q0.size)
+        self.patches = upload_patches(desc, device, dim=dim, p=p, q_out_halo=self.halo,
+                                      q_in_len=q0.size, q_out_len=q0.size, q_in_halo=self.halo)
         self.neighbours = torch.from_numpy(np.ascontiguousarray(neighbours, np.int64)).to(device)
         self.a = torch.from_numpy(q0).to(device)
         self.b = self.a.clone()
         self.per_patch = torch.empty(self.n, dtype=torch.float64, device=device)
         self.lam = torch.empty(1, dtype=torch.float64, device=device)
         self.dt = torch.empty(1, dtype=torch.float64, device=device)
-        max_eigenvalue(self.patches, self.a, self.per_patch, dim=dim, p=p, gamma=gamma)
+        self.dt_next = torch.empty(1, dtype=torch.float64, device=device)
+        self.workspace = torch.zeros(max(3, step_workspace_words(self.n, dim, p)),
+                                     dtype=torch.int64, device=device)
+        max_eigenvalue(self.patches, self.a, self.per_patch, dim=dim, p=p, gamma=gamma,
+                       q_halo=self.halo)
+        if mode == "fused":
+            # the first step's dt; later ones come out of the fused launch
+            cfl_timestep(self.patches, self.per_patch, dim=dim, cfl=cfl, lambda_out=self.lam,
+                         dt_out=self.dt)
 
-    def step(self, stream=None):
+    def cfl_step(self, stream=None):
+        if self.mode == "fused":
+            return  # computed by the previous fused launch (or the constructor)
         cfl_timestep(self.patches, self.per_patch, dim=self.dim, cfl=self.cfl,
                      lambda_out=self.lam, dt_out=self.dt, stream=stream)
-        batch_update(self.patches, self.a, self.b, dim=self.dim, p=self.p, gamma=self.gamma,
-                     q_out_halo=True, dt=self.dt, max_eig=self.per_patch, stream=stream)
-        fill_halo(self.patches, self.neighbours, self.b, dim=self.dim, p=self.p, stream=stream)
+
+    def update(self, stream=None):
+        if self.mode == "halo":
+            batch_update(self.patches, self.a, self.b, dim=self.dim, p=self.p, gamma=self.gamma,
+                         q_out_halo=True, dt=self.dt, max_eig=self.per_patch, stream=stream)
+        elif self.mode == "gather":
+            batch_update_gather(self.patches, self.neighbours, self.a, self.b, dim=self.dim,
+                                p=self.p, gamma=self.gamma, q_out_halo=False, dt=self.dt,
+                                max_eig=self.per_patch, stream=stream)
+        else:
+            step_gather(self.patches, self.neighbours, self.a, self.b, self.dt, self.dt_next,
+                        self.workspace, dim=self.dim, p=self.p, gamma=self.gamma, cfl=self.cfl,
+                        max_eig=self.per_patch, lambda_out=self.lam, stream=stream)
+
+    def exchange(self, stream=None):
+        if self.halo:
+            fill_halo(self.patches, self.neighbours, self.b, dim=self.dim, p=self.p,
+                      stream=stream)
+
+    def swap(self):
+        """Swap the state buffers (and, fused, the dt buffers): the new state
+        becomes the input of the next step."""
         self.a, self.b = self.b, self.a
+        if self.mode == "fused":
+            self.dt, self.dt_next = self.dt_next, self.dt
+
+    def step(self, stream=None):
+        self.cfl_step(stream)
+        self.update(stream)
+        self.exchange(stream)
+        self.swap()
+
+    def last_dt(self):
+        """Device tensor holding the time step used by the most recent step."""
+        return self.dt_next if self.mode == "fused" else self.dt
 
     def state(self):
         return self.a

@@ -111,9 +111,9 @@ class PatchGrid:
         return self.n * (blk + gap)
 
     def descriptors(self, dt: float = 0.0, out_halo: bool = True, in_order=None,
-                    out_order=None, gap: int = 0) -> np.ndarray:
+                    out_order=None, gap: int = 0, in_halo: bool = True) -> np.ndarray:
         desc = np.zeros(self.n, dtype=PATCH_DTYPE)
-        desc["q_in"] = self.offsets(True, in_order, gap)
+        desc["q_in"] = self.offsets(in_halo, in_order, gap)
         desc["q_out"] = self.offsets(out_halo, out_order, gap)
         desc["p"] = self.p
         desc["dx"][:, : self.d] = self.dx
@@ -189,6 +189,21 @@ class PatchGrid:
         off = self.offsets(True, order, gap)
         for b in range(self.n):
             out[off[b]: off[b] + self.block_halo] = blocks[b]
+        return out
+
+    def pack_compact(self, glob: np.ndarray, order=None, gap: int = 0,
+                     fill=np.nan) -> np.ndarray:
+        """Global grid [s][...] -> flat buffer of compact blocks [s][p^d] (no halo)."""
+        w = self.p + 2
+        blocks = self.pack(glob).reshape(self.n, self.s, *([w] * self.d))
+        inner = (slice(None), slice(None)) + (slice(1, -1),) * self.d
+        blocks = np.ascontiguousarray(blocks[inner]).reshape(self.n, -1)
+        if order is None and gap == 0:
+            return blocks.reshape(-1).copy()
+        out = np.full(self.buffer_len(False, gap), fill, dtype=np.float64)
+        off = self.offsets(False, order, gap)
+        for b in range(self.n):
+            out[off[b]: off[b] + self.block_compact] = blocks[b]
         return out
 
     def unpack(self, flat: np.ndarray, halo: bool = True, order=None,

@@ -80,6 +80,12 @@ def test_check_patches_accepts_valid_and_names_bad_patch():
     fv.check_patches(desc2, 3, 8, False, L, g2.buffer_len(False))
     with pytest.raises(fv.FVError):
         fv.check_patches(desc2, 3, 8, False, L, g2.buffer_len(False) - 1)
+    # compact input blocks
+    desc3 = g2.descriptors(out_halo=False, in_halo=False)
+    Lc = g2.buffer_len(False)
+    fv.check_patches(desc3, 3, 8, False, Lc, Lc, q_in_halo=False)
+    with pytest.raises(fv.FVError, match="input block"):
+        fv.check_patches(desc3, 3, 8, False, Lc, Lc, q_in_halo=True)
 
 
 def _call_update(**kw):
@@ -126,3 +132,19 @@ def test_other_entry_points_reject_bad_arguments_on_host():
     assert lib.fv_fill_halo(0x1000, 4, None, 0x2000, 100, 0, 3, 8, 1, 5, None) == fv.FV_EINVAL
     assert lib.fv_fill_halo(0x1000, 4, 0x3000, 0x2000, 100, 0, 3, 3, 1, 5,
                             None) == fv.FV_EUNSUPPORTED
+
+
+def test_step_workspace_size_and_rejection_on_host():
+    lib = fv.library()
+    assert fv.step_workspace_words(4096, 3, 8) == 32 * (1 + 64)
+    assert fv.step_workspace_words(64, 2, 16) == 32 * 2   # 4 patches per workgroup
+    assert fv.step_workspace_words(0, 3, 8) == 0 and fv.step_workspace_words(10, 3, 5) == 0
+    args = [0x1000, 4096, 0x2000, 0x10000, 1000, 0x100000, 1000, 3, 8, 5, 1.4, 0.4, 0x3000, None,
+            0x4000]
+    # too small a workspace is refused before any launch
+    assert lib.fv_step_gather(*args, None, 0x5000, 2079, None) == fv.FV_EINVAL
+    assert "workspace" in lib.fv_last_error().decode()
+    # dt_next may not alias dt
+    bad = list(args)
+    bad[14] = 0x3000
+    assert lib.fv_step_gather(*bad, None, 0x5000, 4096, None) == fv.FV_EINVAL

@@ -177,31 +177,123 @@ def test_c2_full_size_one_step(c2):
     np.testing.assert_allclose(me, me_ref, rtol=LAM_TOL)
 
 
-def run_gpu_steps(grid, flat, steps):
+def run_gpu_steps(grid, q_glob, steps, mode):
+    """Stepper run; returns the state as a global grid, the dt sequence, the stepper."""
     import torch
-    st = fv.Stepper(grid.descriptors(), grid.neighbours(), flat, dim=grid.d, p=grid.p)
+    halo = mode == "halo"
+    flat = grid.pack(q_glob) if halo else grid.pack_compact(q_glob)
+    desc = grid.descriptors(out_halo=halo, in_halo=halo)
+    st = fv.Stepper(desc, grid.neighbours(), flat, dim=grid.d, p=grid.p, mode=mode)
     dts = []
     for _ in range(steps):
         st.step()
-        dts.append(st.dt.item())
+        dts.append(st.last_dt().item())
     torch.cuda.synchronize()
-    return st.state().cpu().numpy(), dts, st
+    return grid.unpack(st.state().cpu().numpy(), halo=halo), dts, st
 
 
-def test_c2_full_size_ten_steps_with_halo_and_cfl(c2):
-    _say("[c2 3d 4096x8^3 ten steps]")
+@pytest.mark.parametrize("mode", ["fused", "gather", "halo"])
+def test_c2_full_size_ten_steps_with_halo_and_cfl(c2, mode):
+    _say(f"[c2 3d 4096x8^3 ten steps, mode={mode}]")
     grid, flat = c2
-    got, dts = run_gpu_steps(grid, flat, 10)[:2]
+    got, dts, st = run_gpu_steps(grid, grid.unpack(flat), 10, mode)
     ref, _, dts_ref = oracle.run_steps(grid.offsets(), np.full((grid.n, 3), grid.dx), flat,
                                        grid.neighbours(), 3, 8, 10, nthreads=0)
     np.testing.assert_allclose(dts, dts_ref, rtol=1e-13)
-    err = normwise(grid.unpack(got), grid.unpack(ref), 5)
+    err = normwise(got, grid.unpack(ref), 5)
     _say(f"    err after 10 steps = {err:.3e}")
     assert err <= TOL
-    # the halo of the GPU state was filled by the GPU halo kernel
-    np.testing.assert_array_equal(np.isnan(got), np.isnan(ref))
-    m = ~np.isnan(ref)
-    assert np.abs(got[m] - ref[m]).max() <= TOL * np.abs(ref[m]).max()
+    if mode == "halo":
+        # the halo of the GPU state was filled by the GPU halo kernel
+        full = st.state().cpu().numpy()
+        np.testing.assert_array_equal(np.isnan(full), np.isnan(ref))
+        m = ~np.isnan(ref)
+        assert np.abs(full[m] - ref[m]).max() <= TOL * np.abs(ref[m]).max()
+
+
+@pytest.mark.parametrize("d,p,counts,bc", [
+    (3, 8, (4, 3, 2), ("periodic",) * 3),
+    (3, 8, (3, 2, 2), ("transmissive", "periodic", "transmissive")),
+    (3, 4, (3, 3, 2), ("transmissive", "transmissive", "periodic")),
+    (3, 16, (2, 1, 2), ("periodic", "transmissive", "periodic")),
+    (2, 16, (3, 2), ("transmissive", "periodic")),
+    (2, 17, (2, 3), ("periodic", "transmissive")),
+    (2, 4, (5, 3), ("periodic", "periodic")),
+    (2, 32, (2, 2), ("transmissive", "transmissive")),
+])
+def test_gather_equals_halo_path_bitwise(d, p, counts, bc):
+    """The fused gather reads exactly the values the halo fill would copy."""
+    _say(f"[gather == halo d={d} p={p} bc={bc}]")
+    rng = np.random.default_rng(7 * p + d)
+    grid = W.PatchGrid(d, p, counts, 1.0 / (counts[0] * p), bc)
+    shape = grid.shape
+    q = W.to_conserved(rng.uniform(0.5, 1.5, shape), [rng.uniform(-0.5, 0.5, shape) for _ in range(d)],
+                       rng.uniform(0.5, 2.0, shape))
+    dt = first_dt(grid, grid.pack(q))
+    a, me_a = gpu_step(grid, grid.pack(q), grid.descriptors(dt=dt, out_halo=False),
+                       out_halo=False)
+    import torch
+    desc_g = grid.descriptors(dt=dt, out_halo=False, in_halo=False)
+    qin = to_dev(grid.pack_compact(q))
+    qout = torch.full((grid.buffer_len(False),), -123.0, dtype=torch.float64, device="cuda")
+    me = torch.empty(grid.n, dtype=torch.float64, device="cuda")
+    fv.batch_update_gather(fv.upload_patches(desc_g), to_dev(grid.neighbours()), qin, qout,
+                           dim=d, p=p, dt=None, max_eig=me)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(qout.cpu().numpy(), a)
+    np.testing.assert_array_equal(me.cpu().numpy(), me_a)
+    ref, _ = oracle_step(grid, grid.pack(q), grid.descriptors(dt=dt, out_halo=False),
+                         out_halo=False)
+    assert normwise(a, ref, d + 2) <= TOL
+
+
+def test_fused_step_matches_separate_launches_bitwise():
+    """fv_step_gather == fv_batch_update_gather + fv_cfl_timestep, bit for bit,
+    run to run, and it leaves its workspace zeroed."""
+    _say("[fused step == gather + cfl, determinism, workspace]")
+    grid, q = W.grid_3d_random_smooth(8, 8, seed=21)
+    a, dts_a, st_a = run_gpu_steps(grid, q, 6, "fused")
+    b, dts_b, _ = run_gpu_steps(grid, q, 6, "gather")
+    c, dts_c, _ = run_gpu_steps(grid, q, 6, "fused")
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(dts_a, dts_b)
+    np.testing.assert_array_equal(a, c)
+    np.testing.assert_array_equal(dts_a, dts_c)
+    assert (st_a.workspace.cpu().numpy() == 0).all()
+    assert st_a.lam.item() == st_a.per_patch.max().item()
+
+
+def test_fused_step_nan_gives_nan_dt():
+    import torch
+    _say("[fused step NaN -> NaN dt]")
+    grid, q = W.grid_3d_random_smooth(2, 8, seed=22)
+    bad = q.copy()
+    bad[0, 3, 3, 3] = np.nan
+    st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
+                    grid.pack_compact(bad), dim=3, p=8, mode="fused")
+    st.step()
+    torch.cuda.synchronize()
+    assert math.isnan(st.dt.item()) and math.isnan(st.lam.item())
+    assert (st.workspace.cpu().numpy() == 0).all()
+
+
+def test_gather_bad_neighbours_are_flagged():
+    import torch
+    _say("[gather: bad neighbour entries]")
+    grid, q = W.grid_3d_random_smooth(2, 8, seed=12)
+    desc = grid.descriptors(dt=1e-4, out_halo=False, in_halo=False)
+    nb = grid.neighbours()
+    nb[3, 1] = grid.n      # out of range
+    nb[5, 4] = -2          # invalid code
+    qin = to_dev(grid.pack_compact(q))
+    qout = torch.full((grid.buffer_len(False),), -123.0, dtype=torch.float64, device="cuda")
+    me = torch.empty(grid.n, dtype=torch.float64, device="cuda")
+    fv.batch_update_gather(fv.upload_patches(desc), to_dev(nb), qin, qout, dim=3, p=8, max_eig=me)
+    torch.cuda.synchronize()
+    me = me.cpu().numpy()
+    assert np.isnan(me[3]) and np.isnan(me[5]) and np.isfinite(np.delete(me, [3, 5])).all()
+    out = qout.cpu().numpy().reshape(grid.n, -1)
+    assert (out[3] == -123.0).all() and (out[5] == -123.0).all()
 
 
 # ---------------------------------------------------------------------------
@@ -211,30 +303,30 @@ def test_sod_512_patches_parity_first_steps():
     _say("[sod 512 patches, 20 steps vs oracle]")
     grid, q = W.grid_sod()
     flat = grid.pack(q)
-    got, dts = run_gpu_steps(grid, flat, 20)[:2]
     ref, _, dts_ref = oracle.run_steps(grid.offsets(), np.full((grid.n, 3), grid.dx), flat,
                                        grid.neighbours(), 3, 8, 20)
-    np.testing.assert_allclose(dts, dts_ref, rtol=1e-13)
-    assert normwise(grid.unpack(got), grid.unpack(ref), 5) <= TOL
+    for mode in ("fused", "gather", "halo"):
+        got, dts = run_gpu_steps(grid, q, 20, mode)[:2]
+        np.testing.assert_allclose(dts, dts_ref, rtol=1e-13)
+        assert normwise(got, grid.unpack(ref), 5) <= TOL
 
 
 def _gpu_sod_l1(px):
     import torch
     grid, q = W.grid_sod(d=3, px=px, pt=2, p=8)
-    st = fv.Stepper(grid.descriptors(), grid.neighbours(), grid.pack(q), dim=3, p=8)
+    desc = grid.descriptors(out_halo=False, in_halo=False)
+    st = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=3, p=8, mode="gather")
     t, t_end = 0.0, 0.2
     # clip the last step to land on t_end: the host reads dt (fine for a test)
     while t < t_end - 1e-15:
-        fv.cfl_timestep(st.patches, st.per_patch, dim=3, cfl=0.4, dt_out=st.dt)
+        st.cfl_step()
         dt = min(st.dt.item(), t_end - t)
         st.dt.fill_(dt)
-        fv.batch_update(st.patches, st.a, st.b, dim=3, p=8, q_out_halo=True, dt=st.dt,
-                        max_eig=st.per_patch)
-        fv.fill_halo(st.patches, st.neighbours, st.b, dim=3, p=8)
-        st.a, st.b = st.b, st.a
+        st.update()
+        st.swap()
         t += dt
     torch.cuda.synchronize()
-    g = grid.unpack(st.state().cpu().numpy())
+    g = grid.unpack(st.state().cpu().numpy(), halo=False)
     rho = g[0].reshape(-1, g.shape[-1])
     assert (rho == rho[0]).all(), "y/z slices of a 1-D problem must stay identical"
     faces = np.arange(g.shape[-1] + 1) * grid.dx
