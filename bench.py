@@ -169,6 +169,47 @@ def plain_path(grid, q, steps):
             "update_hbm_frac": bpc * grid.cells / (upd_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def fp32_path(grid, q, steps, warmup, ref_state):
+    """The same fused step with FP32 state (FP64 maxima / CFL): throughput, kernel
+    time, roofline at the FP32 algorithmic bytes, and the relative difference
+    to the FP64 state after the same number of steps."""
+    import torch
+    from paper_2302_09005_amd import fv
+    st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
+                    grid.pack_compact(q), dim=grid.d, p=grid.p, mode="fused", dtype=np.float32)
+    for _ in range(warmup):
+        st.step()
+    hip = HipEvents(steps)
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for i in range(steps):
+        fv.set_launch_events(hip.start[i], hip.stop[i])
+        st.update()
+        st.swap()
+    fv.set_launch_events(None, None)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    upd = hip.elapsed_ms()
+    hip.destroy()
+    total = t0.elapsed_time(t1)
+    a = st.state().double()
+    r = ref_state
+    s = grid.s
+    d = (a - r).view(s, -1)
+    rv = r.view(s, -1)
+    l2 = float((d.norm(dim=1) / rv.norm(dim=1)).max())
+    li = float((d.abs().amax(dim=1) / rv.abs().amax(dim=1)).max())
+    bpc = algorithmic_bytes_per_cell(grid.d, grid.p, grid.s, 4)
+    return {"steps": steps, "cell_updates_per_s": grid.cells * steps / (total * 1e-3),
+            "ms_per_step": total / steps, "update_us": float(upd.mean() * 1e3),
+            "algorithmic_bytes_per_cell": bpc,
+            "update_hbm_frac": bpc * grid.cells / (upd.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "rel_l2_vs_fp64": l2, "rel_linf_vs_fp64": li,
+            "speedup_vs_fp64_step": None}
+
+
 def copy_calibration(mib=1024, reps=5):
     """Plain device copy of a known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -248,6 +289,9 @@ def main():
 
     # the paper's interface for comparison: halo'd blocks, update + separate halo fill
     plain = plain_path(grid, q, min(args.steps, 20))
+    # FP32 bulk arithmetic on the same workload and step count
+    f32 = fp32_path(grid, q, args.steps, args.warmup, state)
+    f32["speedup_vs_fp64_step"] = (total_ms / args.steps) / f32["ms_per_step"]
 
     cells = grid.cells
     value = cells * args.steps / (total_ms * 1e-3)
@@ -280,7 +324,8 @@ def main():
         "detail": {"update_cell_updates_per_s": cells / upd_s,
                    "update_us_median": float(np.median(upd_ms) * 1e3),
                    "final_lambda": lam_final, "state_finite": finite,
-                   "plain_halo_path": plain},
+                   "plain_halo_path": plain,
+                   "fp32_path": f32},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid, grid.pack(q), args.cpu_budget, 100)

@@ -195,6 +195,53 @@ int fv_step_gather(const fv_patch* patches, int64_t n_patches, const int64_t* ne
 int64_t fv_step_workspace_words(int64_t n_patches, int dim, int p);
 
 /*
+ * FP32 state (bulk flux and update arithmetic in single precision): the same
+ * operations on float blocks.  The time step, the per-patch maxima written to
+ * max_eig, Lambda and the CFL reduction stay FP64 (double outputs; the FP32
+ * per-volume wave speeds are folded into FP64 maxima).  Arguments as for the
+ * FP64 entry points above.
+ */
+int fv_batch_update_f32(const fv_patch* patches, int64_t n_patches,
+                        const float* q_in, int64_t q_in_len,
+                        float* q_out, int64_t q_out_len, int q_out_halo,
+                        int dim, int p, int halo, int s, double gamma,
+                        const double* dt_dev, double* max_eig, void* stream);
+int fv_batch_update_gather_f32(const fv_patch* patches, int64_t n_patches,
+                               const int64_t* neighbours,
+                               const float* q_in, int64_t q_in_len,
+                               float* q_out, int64_t q_out_len, int q_out_halo,
+                               int dim, int p, int s, double gamma,
+                               const double* dt_dev, double* max_eig, void* stream);
+int fv_step_gather_f32(const fv_patch* patches, int64_t n_patches, const int64_t* neighbours,
+                       const float* q_in, int64_t q_in_len, float* q_out, int64_t q_out_len,
+                       int dim, int p, int s, double gamma, double cfl,
+                       const double* dt_dev, double* max_eig, double* dt_next,
+                       double* lambda_out, uint64_t* workspace, int64_t workspace_words,
+                       void* stream);
+int fv_max_eigenvalue_f32(const fv_patch* patches, int64_t n_patches,
+                          const float* q, int64_t q_len, int q_halo, int which_offsets,
+                          int dim, int p, int s, double gamma,
+                          double* per_patch, double* global, void* stream);
+
+/*
+ * fv_conserved_totals / _f32 -- totals of the conserved unknowns (mass,
+ * momentum, energy: the quantities eq. (3) conserves on a periodic domain)
+ * over the interior volumes of all patches, accumulated in FP64 whatever the
+ * state's precision, in a fixed order (deterministic for a given batch).
+ * per_patch   device double [n_patches * s], required: per-patch totals
+ * totals      device double [s] or NULL: sum over patches
+ * q_halo, which_offsets as for fv_max_eigenvalue.  n_patches >= 1.  A patch
+ * that fails the device-side check gets NaN totals.
+ */
+int fv_conserved_totals(const fv_patch* patches, int64_t n_patches,
+                        const double* q, int64_t q_len, int q_halo, int which_offsets,
+                        int dim, int p, int s, double* per_patch, double* totals, void* stream);
+int fv_conserved_totals_f32(const fv_patch* patches, int64_t n_patches,
+                            const float* q, int64_t q_len, int q_halo, int which_offsets,
+                            int dim, int p, int s, double* per_patch, double* totals,
+                            void* stream);
+
+/*
  * fv_max_eigenvalue -- largest eigenvalue of a given state (Section 2,
  * eq. (5); Algorithm 1 last step), for the first CFL step of a run.
  *

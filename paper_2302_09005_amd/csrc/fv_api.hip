@@ -112,9 +112,25 @@ int fv_check_patches(const fv_patch* host_patches, int64_t n, int dim, int p, in
   return ok();
 }
 
-int fv_batch_update(const fv_patch* patches, int64_t n, const double* q_in, int64_t q_in_len,
-                    double* q_out, int64_t q_out_len, int q_out_halo, int dim, int p, int halo,
-                    int s, double gamma, const double* dt_dev, double* max_eig, void* stream) {
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+int overlap_check(const T* q_in, int64_t q_in_len, const T* q_out, int64_t q_out_len) {
+  const char* a0 = (const char*)q_in;
+  const char* a1 = a0 + q_in_len * (int64_t)sizeof(T);
+  const char* b0 = (const char*)q_out;
+  const char* b1 = b0 + q_out_len * (int64_t)sizeof(T);
+  if (a0 < b1 && b0 < a1) return fail(FV_EINVAL, "q_in and q_out overlap");
+  return FV_OK;
+}
+
+template <typename T>
+int batch_update_impl(const char* name, const fv_patch* patches, int64_t n, const T* q_in,
+                      int64_t q_in_len, T* q_out, int64_t q_out_len, int q_out_halo, int dim,
+                      int p, int halo, int s, double gamma, const double* dt_dev, double* max_eig,
+                      void* stream) {
   int rc = check_shape(dim, p, halo, s);
   if (rc) return rc;
   if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
@@ -124,24 +140,18 @@ int fv_batch_update(const fv_patch* patches, int64_t n, const double* q_in, int6
   if (!patches || !q_in || !q_out) return fail(FV_EINVAL, "null device pointer");
   if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
   if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
-  {
-    // the output range must not overlap the input range
-    const char* a0 = (const char*)q_in;
-    const char* a1 = a0 + q_in_len * (int64_t)sizeof(double);
-    const char* b0 = (const char*)q_out;
-    const char* b1 = b0 + q_out_len * (int64_t)sizeof(double);
-    if (a0 < b1 && b0 < a1) return fail(FV_EINVAL, "q_in and q_out overlap");
-  }
-  rc = fvk::launch_update_f64(patches, n, q_in, q_in_len, q_out, q_out_len, q_out_halo, dim, p,
-                              gamma, dt_dev, max_eig, (hipStream_t)stream);
+  if ((rc = overlap_check(q_in, q_in_len, q_out, q_out_len))) return rc;
+  rc = fvk::launch_update<T>(patches, n, q_in, q_in_len, q_out, q_out_len, q_out_halo, dim, p,
+                             gamma, dt_dev, max_eig, (hipStream_t)stream);
   if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
-  return launched("fv_batch_update");
+  return launched(name);
 }
 
-int fv_batch_update_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours,
-                           const double* q_in, int64_t q_in_len, double* q_out,
-                           int64_t q_out_len, int q_out_halo, int dim, int p, int s,
-                           double gamma, const double* dt_dev, double* max_eig, void* stream) {
+template <typename T>
+int batch_update_gather_impl(const char* name, const fv_patch* patches, int64_t n,
+                             const int64_t* neighbours, const T* q_in, int64_t q_in_len,
+                             T* q_out, int64_t q_out_len, int q_out_halo, int dim, int p, int s,
+                             double gamma, const double* dt_dev, double* max_eig, void* stream) {
   int rc = check_shape(dim, p, 1, s);
   if (rc) return rc;
   if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
@@ -151,18 +161,125 @@ int fv_batch_update_gather(const fv_patch* patches, int64_t n, const int64_t* ne
   if (!patches || !neighbours || !q_in || !q_out) return fail(FV_EINVAL, "null device pointer");
   if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
   if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
-  {
-    const char* a0 = (const char*)q_in;
-    const char* a1 = a0 + q_in_len * (int64_t)sizeof(double);
-    const char* b0 = (const char*)q_out;
-    const char* b1 = b0 + q_out_len * (int64_t)sizeof(double);
-    if (a0 < b1 && b0 < a1) return fail(FV_EINVAL, "q_in and q_out overlap");
-  }
-  rc = fvk::launch_update_gather_f64(patches, n, neighbours, q_in, q_in_len, q_out, q_out_len,
-                                     q_out_halo, dim, p, gamma, dt_dev, max_eig,
-                                     (hipStream_t)stream);
+  if ((rc = overlap_check(q_in, q_in_len, q_out, q_out_len))) return rc;
+  rc = fvk::launch_update_gather<T>(patches, n, neighbours, q_in, q_in_len, q_out, q_out_len,
+                                    q_out_halo, dim, p, gamma, dt_dev, max_eig,
+                                    (hipStream_t)stream);
   if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
-  return launched("fv_batch_update_gather");
+  return launched(name);
+}
+
+template <typename T>
+int step_gather_impl(const char* name, const fv_patch* patches, int64_t n,
+                     const int64_t* neighbours, const T* q_in, int64_t q_in_len, T* q_out,
+                     int64_t q_out_len, int dim, int p, int s, double gamma, double cfl,
+                     const double* dt_dev, double* max_eig, double* dt_next, double* lambda_out,
+                     uint64_t* workspace, int64_t workspace_words, void* stream) {
+  int rc = check_shape(dim, p, 1, s);
+  if (rc) return rc;
+  if (n < 1) return fail(FV_EINVAL, "n_patches must be >= 1");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (!(cfl > 0.0) || !isfinite(cfl)) return fail(FV_EINVAL, "cfl must be finite and > 0");
+  if (!patches || !neighbours || !q_in || !q_out || !dt_dev || !dt_next || !workspace)
+    return fail(FV_EINVAL, "null device pointer");
+  if (dt_next == dt_dev) return fail(FV_EINVAL, "dt_next must not alias dt_dev");
+  const int64_t need = fvk::step_workspace_words(fvk::update_workgroups(dim, p, n));
+  if (workspace_words < need) return fail(FV_EINVAL, "workspace needs %lld words", (long long)need);
+  if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  if ((rc = overlap_check(q_in, q_in_len, q_out, q_out_len))) return rc;
+  fvk::CflOut co;
+  co.cfl = cfl;
+  co.dt_next = dt_next;
+  co.lambda_out = lambda_out;
+  co.ws = reinterpret_cast<unsigned long long*>(workspace);
+  rc = fvk::launch_step_gather<T>(patches, n, neighbours, q_in, q_in_len, q_out, q_out_len, dim,
+                                  p, gamma, dt_dev, max_eig, co, (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  return launched(name);
+}
+
+template <typename T>
+int max_eigenvalue_impl(const char* name, const fv_patch* patches, int64_t n, const T* q,
+                        int64_t q_len, int q_halo, int which, int dim, int p, int s, double gamma,
+                        double* per_patch, double* global, void* stream) {
+  int rc = check_shape(dim, p, 1, s);
+  if (rc) return rc;
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (q_halo != 0 && q_halo != 1) return fail(FV_EINVAL, "q_halo must be 0 or 1");
+  if (which != FV_OFFSETS_IN && which != FV_OFFSETS_OUT)
+    return fail(FV_EINVAL, "which_offsets must be FV_OFFSETS_IN or FV_OFFSETS_OUT");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (n == 0) {
+    if (!global) return ok();
+    // nothing to reduce: the reduction kernel writes the documented 0
+    fvk::launch_reduce_cfl(patches, 0, per_patch, dim, 1.0, global, nullptr, (hipStream_t)stream);
+    return launched(name);
+  }
+  if (!patches || !q || !per_patch) return fail(FV_EINVAL, "null device pointer");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  rc = fvk::launch_patch_max<T>(patches, n, q, q_len, q_halo, which, dim, p, gamma, per_patch,
+                                (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  if (global)
+    fvk::launch_reduce_cfl(patches, n, per_patch, dim, 1.0, global, nullptr, (hipStream_t)stream);
+  return launched(name);
+}
+
+template <typename T>
+int totals_impl(const char* name, const fv_patch* patches, int64_t n, const T* q, int64_t q_len,
+                int q_halo, int which, int dim, int p, int s, double* per_patch, double* totals,
+                void* stream) {
+  int rc = check_shape(dim, p, 1, s);
+  if (rc) return rc;
+  if (n < 1) return fail(FV_EINVAL, "n_patches must be >= 1");
+  if (q_halo != 0 && q_halo != 1) return fail(FV_EINVAL, "q_halo must be 0 or 1");
+  if (which != FV_OFFSETS_IN && which != FV_OFFSETS_OUT)
+    return fail(FV_EINVAL, "which_offsets must be FV_OFFSETS_IN or FV_OFFSETS_OUT");
+  if (!patches || !q || !per_patch) return fail(FV_EINVAL, "null device pointer");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  rc = fvk::launch_totals<T>(patches, n, q, q_len, q_halo, which, dim, p, per_patch, totals,
+                             (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  return launched(name);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fv_batch_update(const fv_patch* patches, int64_t n, const double* q_in, int64_t q_in_len,
+                    double* q_out, int64_t q_out_len, int q_out_halo, int dim, int p, int halo,
+                    int s, double gamma, const double* dt_dev, double* max_eig, void* stream) {
+  return batch_update_impl("fv_batch_update", patches, n, q_in, q_in_len, q_out, q_out_len,
+                           q_out_halo, dim, p, halo, s, gamma, dt_dev, max_eig, stream);
+}
+
+int fv_batch_update_f32(const fv_patch* patches, int64_t n, const float* q_in, int64_t q_in_len,
+                        float* q_out, int64_t q_out_len, int q_out_halo, int dim, int p, int halo,
+                        int s, double gamma, const double* dt_dev, double* max_eig,
+                        void* stream) {
+  return batch_update_impl("fv_batch_update_f32", patches, n, q_in, q_in_len, q_out, q_out_len,
+                           q_out_halo, dim, p, halo, s, gamma, dt_dev, max_eig, stream);
+}
+
+int fv_batch_update_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                           const double* q_in, int64_t q_in_len, double* q_out,
+                           int64_t q_out_len, int q_out_halo, int dim, int p, int s,
+                           double gamma, const double* dt_dev, double* max_eig, void* stream) {
+  return batch_update_gather_impl("fv_batch_update_gather", patches, n, neighbours, q_in,
+                                  q_in_len, q_out, q_out_len, q_out_halo, dim, p, s, gamma,
+                                  dt_dev, max_eig, stream);
+}
+
+int fv_batch_update_gather_f32(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                               const float* q_in, int64_t q_in_len, float* q_out,
+                               int64_t q_out_len, int q_out_halo, int dim, int p, int s,
+                               double gamma, const double* dt_dev, double* max_eig,
+                               void* stream) {
+  return batch_update_gather_impl("fv_batch_update_gather_f32", patches, n, neighbours, q_in,
+                                  q_in_len, q_out, q_out_len, q_out_halo, dim, p, s, gamma,
+                                  dt_dev, max_eig, stream);
 }
 
 int64_t fv_step_workspace_words(int64_t n, int dim, int p) {
@@ -175,62 +292,47 @@ int fv_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours
                    int dim, int p, int s, double gamma, double cfl, const double* dt_dev,
                    double* max_eig, double* dt_next, double* lambda_out, uint64_t* workspace,
                    int64_t workspace_words, void* stream) {
-  int rc = check_shape(dim, p, 1, s);
-  if (rc) return rc;
-  if (n < 1) return fail(FV_EINVAL, "n_patches must be >= 1");
-  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
-  if (!(cfl > 0.0) || !isfinite(cfl)) return fail(FV_EINVAL, "cfl must be finite and > 0");
-  if (!patches || !neighbours || !q_in || !q_out || !dt_dev || !dt_next || !workspace)
-    return fail(FV_EINVAL, "null device pointer");
-  if (dt_next == dt_dev) return fail(FV_EINVAL, "dt_next must not alias dt_dev");
-  if (workspace_words < fv_step_workspace_words(n, dim, p))
-    return fail(FV_EINVAL, "workspace needs %lld words", (long long)fv_step_workspace_words(n, dim, p));
-  if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
-  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
-  {
-    const char* a0 = (const char*)q_in;
-    const char* a1 = a0 + q_in_len * (int64_t)sizeof(double);
-    const char* b0 = (const char*)q_out;
-    const char* b1 = b0 + q_out_len * (int64_t)sizeof(double);
-    if (a0 < b1 && b0 < a1) return fail(FV_EINVAL, "q_in and q_out overlap");
-  }
-  fvk::CflOut co;
-  co.cfl = cfl;
-  co.dt_next = dt_next;
-  co.lambda_out = lambda_out;
-  co.ws = reinterpret_cast<unsigned long long*>(workspace);
-  rc = fvk::launch_step_gather_f64(patches, n, neighbours, q_in, q_in_len, q_out, q_out_len, dim,
-                                   p, gamma, dt_dev, max_eig, co, (hipStream_t)stream);
-  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
-  return launched("fv_step_gather");
+  return step_gather_impl("fv_step_gather", patches, n, neighbours, q_in, q_in_len, q_out,
+                          q_out_len, dim, p, s, gamma, cfl, dt_dev, max_eig, dt_next, lambda_out,
+                          workspace, workspace_words, stream);
+}
+
+int fv_step_gather_f32(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                       const float* q_in, int64_t q_in_len, float* q_out, int64_t q_out_len,
+                       int dim, int p, int s, double gamma, double cfl, const double* dt_dev,
+                       double* max_eig, double* dt_next, double* lambda_out,
+                       uint64_t* workspace, int64_t workspace_words, void* stream) {
+  return step_gather_impl("fv_step_gather_f32", patches, n, neighbours, q_in, q_in_len, q_out,
+                          q_out_len, dim, p, s, gamma, cfl, dt_dev, max_eig, dt_next, lambda_out,
+                          workspace, workspace_words, stream);
 }
 
 int fv_max_eigenvalue(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,
                       int q_halo, int which, int dim, int p, int s, double gamma,
                       double* per_patch, double* global, void* stream) {
-  int rc = check_shape(dim, p, 1, s);
-  if (rc) return rc;
-  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
-  if (q_halo != 0 && q_halo != 1) return fail(FV_EINVAL, "q_halo must be 0 or 1");
-  if (which != FV_OFFSETS_IN && which != FV_OFFSETS_OUT)
-    return fail(FV_EINVAL, "which_offsets must be FV_OFFSETS_IN or FV_OFFSETS_OUT");
-  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
-  if (n == 0) {
-    if (!global) return ok();
-    // nothing to reduce: the reduction kernel writes the documented 0
-    fvk::launch_reduce_cfl(patches, 0, per_patch, dim, 1.0, global, nullptr, (hipStream_t)stream);
-    return launched("fv_max_eigenvalue");
-  }
-  if (!patches || !q || !per_patch) return fail(FV_EINVAL, "null device pointer");
-  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
-  rc = fvk::launch_patch_max_f64(patches, n, q, q_len, q_halo, which, dim, p, gamma, per_patch,
-                                 (hipStream_t)stream);
-  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
-  if (global) {
-    rc = fvk::launch_reduce_cfl(patches, n, per_patch, dim, 1.0, global, nullptr,
-                                (hipStream_t)stream);
-  }
-  return launched("fv_max_eigenvalue");
+  return max_eigenvalue_impl("fv_max_eigenvalue", patches, n, q, q_len, q_halo, which, dim, p, s,
+                             gamma, per_patch, global, stream);
+}
+
+int fv_max_eigenvalue_f32(const fv_patch* patches, int64_t n, const float* q, int64_t q_len,
+                          int q_halo, int which, int dim, int p, int s, double gamma,
+                          double* per_patch, double* global, void* stream) {
+  return max_eigenvalue_impl("fv_max_eigenvalue_f32", patches, n, q, q_len, q_halo, which, dim, p,
+                             s, gamma, per_patch, global, stream);
+}
+
+int fv_conserved_totals(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,
+                        int q_halo, int which, int dim, int p, int s, double* per_patch,
+                        double* totals, void* stream) {
+  return totals_impl("fv_conserved_totals", patches, n, q, q_len, q_halo, which, dim, p, s,
+                     per_patch, totals, stream);
+}
+
+int fv_conserved_totals_f32(const fv_patch* patches, int64_t n, const float* q, int64_t q_len,
+                            int q_halo, int which, int dim, int p, int s, double* per_patch,
+                            double* totals, void* stream) {
+  return totals_impl("fv_conserved_totals_f32", patches, n, q, q_len, q_halo, which, dim, p, s,
+                     per_patch, totals, stream);
 }
 
 int fv_cfl_timestep(const fv_patch* patches, int64_t n, const double* per_patch, int dim,

@@ -69,23 +69,29 @@ struct LaunchEvents {
 LaunchEvents& launch_events();
 
 // Status for launchers: 0 ok, FV_EUNSUPPORTED when (dim, p) has no instance.
-int launch_update_f64(const fv_patch* patches, int64_t n, const double* qin, int64_t qin_len,
-                      double* qout, int64_t qout_len, int out_halo, int dim, int p,
-                      double gamma, const double* dt_dev, double* max_eig, hipStream_t st);
+// Update launchers, instantiated for double and float state.
+template <typename T>
+int launch_update(const fv_patch* patches, int64_t n, const T* qin, int64_t qin_len, T* qout,
+                  int64_t qout_len, int out_halo, int dim, int p, double gamma,
+                  const double* dt_dev, double* max_eig, hipStream_t st);
+template <typename T>
+int launch_update_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                         const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int out_halo,
+                         int dim, int p, double gamma, const double* dt_dev, double* max_eig,
+                         hipStream_t st);
+template <typename T>
+int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                       const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int dim, int p,
+                       double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
+                       hipStream_t st);
 
-int launch_update_gather_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
-                             const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
-                             int out_halo, int dim, int p, double gamma, const double* dt_dev,
-                             double* max_eig, hipStream_t st);
+template <typename T>
+int launch_patch_max(const fv_patch* patches, int64_t n, const T* q, int64_t q_len, int q_halo,
+                     int which, int dim, int p, double gamma, double* per_patch, hipStream_t st);
 
-int launch_step_gather_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
-                           const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
-                           int dim, int p, double gamma, const double* dt_dev, double* max_eig,
-                           const CflOut& cflo, hipStream_t st);
-
-int launch_patch_max_f64(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,
-                         int q_halo, int which, int dim, int p, double gamma,
-                         double* per_patch, hipStream_t st);
+template <typename T>
+int launch_totals(const fv_patch* patches, int64_t n, const T* q, int64_t q_len, int q_halo,
+                  int which, int dim, int p, double* per_patch, double* totals, hipStream_t st);
 
 int launch_reduce_cfl(const fv_patch* patches, int64_t n, const double* per_patch, int dim,
                       double cfl, double* lambda_out, double* dt_out, hipStream_t st);

@@ -24,10 +24,10 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-template <int D, int P>
+template <typename T, int D, int P>
 __global__ void __launch_bounds__(kRedThreads)
-patch_max_kernel(const fv_patch* __restrict__ patches, int64_t n, const double* __restrict__ q,
-                 int64_t q_len, int q_halo, int which, double gamma,
+patch_max_kernel(const fv_patch* __restrict__ patches, int64_t n, const T* __restrict__ q,
+                 int64_t q_len, int q_halo, int which, T gamma,
                  double* __restrict__ per_patch) {
   constexpr int S = D + 2;
   __shared__ double red[kRedThreads / 64];
@@ -39,28 +39,98 @@ patch_max_kernel(const fv_patch* __restrict__ patches, int64_t n, const double* 
   const int o = q_halo ? 1 : 0;
   const int64_t vol = q_halo ? (int64_t)ipow(P + 2, D) : (int64_t)ipow(P, D);
   const bool ok = pd.p == P && off >= 0 && off <= q_len - S * vol;
-  double lam = 0.0;
+  T lam = T(0);
   if (ok) {
-    const double* blk = q + off;
+    const T* blk = q + off;
     for (int i = threadIdx.x; i < ipow(P, D); i += kRedThreads) {
       const int x = i % P;
       const int y = (i / P) % P;
       const int z = D == 3 ? i / (P * P) : 0;
       const int64_t idx = (x + o) + (int64_t)w * (y + o) + (D == 3 ? (int64_t)w * w * (z + o) : 0);
-      double qv[S];
+      T qv[S];
 #pragma unroll
       for (int m = 0; m < S; ++m) qv[m] = blk[(int64_t)m * vol + idx];
-      const Prim<double> wv = decode<double, D>(qv, gamma);
-      lam = nanmax_pos(lam, max_wave_speed<double, D>(qv, wv));
+      const Prim<T> wv = decode<T, D>(qv, gamma);
+      lam = nanmax_pos(lam, max_wave_speed<T, D>(qv, wv));
     }
   }
-  lam = wave_max(lam);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lam;
+  double lamd = wave_max(double(lam));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lamd;
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 1; i < kRedThreads / 64; ++i) lam = nanmax_pos(lam, red[i]);
-    per_patch[b] = ok ? lam : __builtin_nan("");
+    for (int i = 1; i < kRedThreads / 64; ++i) lamd = nanmax_pos(lamd, red[i]);
+    per_patch[b] = ok ? lamd : __builtin_nan("");
+  }
+}
+
+// Conserved totals in FP64 whatever the state's precision: one workgroup per
+// patch sums its interior volumes per unknown (fixed order: strided partial
+// sums, then a fixed shuffle tree), then one workgroup sums the patches in a
+// fixed order.  Deterministic for a given batch.
+template <typename T, int D, int P>
+__global__ void __launch_bounds__(kRedThreads)
+patch_totals_kernel(const fv_patch* __restrict__ patches, int64_t n, const T* __restrict__ q,
+                    int64_t q_len, int q_halo, int which, double* __restrict__ per_patch) {
+  constexpr int S = D + 2;
+  __shared__ double red[S][kRedThreads / 64];
+  const int64_t b = blockIdx.x;
+  if (b >= n) return;
+  const fv_patch pd = patches[b];
+  const int64_t off = which == FV_OFFSETS_OUT ? pd.q_out : pd.q_in;
+  const int w = q_halo ? P + 2 : P;
+  const int o = q_halo ? 1 : 0;
+  const int64_t vol = q_halo ? (int64_t)ipow(P + 2, D) : (int64_t)ipow(P, D);
+  const bool ok = pd.p == P && off >= 0 && off <= q_len - S * vol;
+  double acc[S];
+#pragma unroll
+  for (int m = 0; m < S; ++m) acc[m] = 0.0;
+  if (ok) {
+    const T* blk = q + off;
+    for (int i = threadIdx.x; i < ipow(P, D); i += kRedThreads) {
+      const int x = i % P;
+      const int y = (i / P) % P;
+      const int z = D == 3 ? i / (P * P) : 0;
+      const int64_t idx = (x + o) + (int64_t)w * (y + o) + (D == 3 ? (int64_t)w * w * (z + o) : 0);
+#pragma unroll
+      for (int m = 0; m < S; ++m) acc[m] += double(blk[(int64_t)m * vol + idx]);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < S; ++m) {
+    double v = acc[m];
+#pragma unroll
+    for (int off2 = 32; off2 > 0; off2 >>= 1) v += __shfl_xor(v, off2, 64);
+    if ((threadIdx.x & 63) == 0) red[m][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < S; ++m) {
+      double v = red[m][0];
+      for (int i = 1; i < kRedThreads / 64; ++i) v += red[m][i];
+      per_patch[b * S + m] = ok ? v : __builtin_nan("");
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+sum_patches_kernel(const double* __restrict__ per_patch, int64_t n, int s,
+                   double* __restrict__ totals) {
+  __shared__ double red[16];
+  for (int m = 0; m < s; ++m) {
+    double v = 0.0;
+    for (int64_t b = threadIdx.x; b < n; b += blockDim.x) v += per_patch[b * s + m];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = red[0];
+      for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+      totals[m] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -109,22 +179,29 @@ reduce_cfl_kernel(const fv_patch* __restrict__ patches, int64_t n,
   }
 }
 
-template <int D, int P>
-void launch_pm(const fv_patch* patches, int64_t n, const double* q, int64_t q_len, int q_halo,
+template <typename T, int D, int P>
+void launch_pm(const fv_patch* patches, int64_t n, const T* q, int64_t q_len, int q_halo,
                int which, double gamma, double* per_patch, hipStream_t st) {
-  hipLaunchKernelGGL((patch_max_kernel<D, P>), dim3((unsigned)n), dim3(kRedThreads), 0, st,
-                     patches, n, q, q_len, q_halo, which, gamma, per_patch);
+  hipLaunchKernelGGL((patch_max_kernel<T, D, P>), dim3((unsigned)n), dim3(kRedThreads), 0, st,
+                     patches, n, q, q_len, q_halo, which, T(gamma), per_patch);
+}
+
+template <typename T, int D, int P>
+void launch_tot(const fv_patch* patches, int64_t n, const T* q, int64_t q_len, int q_halo,
+                int which, double* per_patch, hipStream_t st) {
+  hipLaunchKernelGGL((patch_totals_kernel<T, D, P>), dim3((unsigned)n), dim3(kRedThreads), 0, st,
+                     patches, n, q, q_len, q_halo, which, per_patch);
 }
 
 }  // namespace
 
-int launch_patch_max_f64(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,
-                         int q_halo, int which, int dim, int p, double gamma,
-                         double* per_patch, hipStream_t st) {
-#define FV_CASE(DD, PP)                                                                \
-  if (dim == DD && p == PP) {                                                          \
-    launch_pm<DD, PP>(patches, n, q, q_len, q_halo, which, gamma, per_patch, st);      \
-    return 0;                                                                          \
+template <typename T>
+int launch_patch_max(const fv_patch* patches, int64_t n, const T* q, int64_t q_len, int q_halo,
+                     int which, int dim, int p, double gamma, double* per_patch, hipStream_t st) {
+#define FV_CASE(DD, PP)                                                                 \
+  if (dim == DD && p == PP) {                                                           \
+    launch_pm<T, DD, PP>(patches, n, q, q_len, q_halo, which, gamma, per_patch, st);    \
+    return 0;                                                                           \
   }
   FV_CASE(2, 4)
   FV_CASE(2, 8)
@@ -137,6 +214,39 @@ int launch_patch_max_f64(const fv_patch* patches, int64_t n, const double* q, in
 #undef FV_CASE
   return FV_EUNSUPPORTED;
 }
+
+template <typename T>
+int launch_totals(const fv_patch* patches, int64_t n, const T* q, int64_t q_len, int q_halo,
+                  int which, int dim, int p, double* per_patch, double* totals, hipStream_t st) {
+  int rc = FV_EUNSUPPORTED;
+#define FV_CASE(DD, PP)                                                           \
+  if (dim == DD && p == PP) {                                                     \
+    launch_tot<T, DD, PP>(patches, n, q, q_len, q_halo, which, per_patch, st);    \
+    rc = 0;                                                                       \
+  }
+  FV_CASE(2, 4)
+  FV_CASE(2, 8)
+  FV_CASE(2, 16)
+  FV_CASE(2, 17)
+  FV_CASE(2, 32)
+  FV_CASE(3, 4)
+  FV_CASE(3, 8)
+  FV_CASE(3, 16)
+#undef FV_CASE
+  if (rc == 0 && totals)
+    hipLaunchKernelGGL(sum_patches_kernel, dim3(1), dim3(1024), 0, st, per_patch, n, dim + 2,
+                       totals);
+  return rc;
+}
+
+template int launch_patch_max<double>(const fv_patch*, int64_t, const double*, int64_t, int, int,
+                                      int, int, double, double*, hipStream_t);
+template int launch_patch_max<float>(const fv_patch*, int64_t, const float*, int64_t, int, int,
+                                     int, int, double, double*, hipStream_t);
+template int launch_totals<double>(const fv_patch*, int64_t, const double*, int64_t, int, int,
+                                   int, int, double*, double*, hipStream_t);
+template int launch_totals<float>(const fv_patch*, int64_t, const float*, int64_t, int, int, int,
+                                  int, double*, double*, hipStream_t);
 
 int launch_reduce_cfl(const fv_patch* patches, int64_t n, const double* per_patch, int dim,
                       double cfl, double* lambda_out, double* dt_out, hipStream_t st) {

@@ -475,15 +475,15 @@ int launch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin,
   return 0;
 }
 
-template <bool GATHER, bool CFL>
-int dispatch(const fv_patch* patches, int64_t n, const int64_t* nbr, const double* qin,
-             int64_t qin_len, double* qout, int64_t qout_len, int out_halo, int dim, int p,
+template <typename T, bool GATHER, bool CFL>
+int dispatch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin,
+             int64_t qin_len, T* qout, int64_t qout_len, int out_halo, int dim, int p,
              double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
              hipStream_t st) {
-#define FV_CASE(DD, PP)                                                                     \
-  if (dim == DD && p == PP)                                                                 \
-    return launch<double, DD, PP, GATHER, CFL>(patches, n, nbr, qin, qin_len, qout, qout_len, \
-                                               out_halo, gamma, dt_dev, max_eig, cflo, st);
+#define FV_CASE(DD, PP)                                                                   \
+  if (dim == DD && p == PP)                                                               \
+    return launch<T, DD, PP, GATHER, CFL>(patches, n, nbr, qin, qin_len, qout, qout_len,  \
+                                          out_halo, T(gamma), dt_dev, max_eig, cflo, st);
   FV_CASE(2, 4)
   FV_CASE(2, 8)
   FV_CASE(2, 16)
@@ -519,27 +519,43 @@ bool update_supported(int dim, int p) {
   return false;
 }
 
-int launch_update_f64(const fv_patch* patches, int64_t n, const double* qin, int64_t qin_len,
-                      double* qout, int64_t qout_len, int out_halo, int dim, int p,
-                      double gamma, const double* dt_dev, double* max_eig, hipStream_t st) {
-  return dispatch<false, false>(patches, n, nullptr, qin, qin_len, qout, qout_len, out_halo, dim,
-                                p, gamma, dt_dev, max_eig, CflOut{}, st);
+template <typename T>
+int launch_update(const fv_patch* patches, int64_t n, const T* qin, int64_t qin_len, T* qout,
+                  int64_t qout_len, int out_halo, int dim, int p, double gamma,
+                  const double* dt_dev, double* max_eig, hipStream_t st) {
+  return dispatch<T, false, false>(patches, n, nullptr, qin, qin_len, qout, qout_len, out_halo,
+                                   dim, p, gamma, dt_dev, max_eig, CflOut{}, st);
 }
 
-int launch_update_gather_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
-                             const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
-                             int out_halo, int dim, int p, double gamma, const double* dt_dev,
-                             double* max_eig, hipStream_t st) {
-  return dispatch<true, false>(patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo,
-                               dim, p, gamma, dt_dev, max_eig, CflOut{}, st);
+template <typename T>
+int launch_update_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                         const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int out_halo,
+                         int dim, int p, double gamma, const double* dt_dev, double* max_eig,
+                         hipStream_t st) {
+  return dispatch<T, true, false>(patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo,
+                                  dim, p, gamma, dt_dev, max_eig, CflOut{}, st);
 }
 
-int launch_step_gather_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
-                           const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
-                           int dim, int p, double gamma, const double* dt_dev, double* max_eig,
-                           const CflOut& cflo, hipStream_t st) {
-  return dispatch<true, true>(patches, n, neighbours, qin, qin_len, qout, qout_len, 0, dim, p,
-                              gamma, dt_dev, max_eig, cflo, st);
+template <typename T>
+int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                       const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int dim, int p,
+                       double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
+                       hipStream_t st) {
+  return dispatch<T, true, true>(patches, n, neighbours, qin, qin_len, qout, qout_len, 0, dim, p,
+                                 gamma, dt_dev, max_eig, cflo, st);
 }
+
+#define FV_INSTANTIATE(T)                                                                     \
+  template int launch_update<T>(const fv_patch*, int64_t, const T*, int64_t, T*, int64_t, int,  \
+                                int, int, double, const double*, double*, hipStream_t);        \
+  template int launch_update_gather<T>(const fv_patch*, int64_t, const int64_t*, const T*,      \
+                                       int64_t, T*, int64_t, int, int, int, double,             \
+                                       const double*, double*, hipStream_t);                    \
+  template int launch_step_gather<T>(const fv_patch*, int64_t, const int64_t*, const T*,        \
+                                     int64_t, T*, int64_t, int, int, double, const double*,     \
+                                     double*, const CflOut&, hipStream_t);
+FV_INSTANTIATE(double)
+FV_INSTANTIATE(float)
+#undef FV_INSTANTIATE
 
 }  // namespace fvk

@@ -71,6 +71,14 @@ def library():
     lib.fv_step_workspace_words.restype = i64
     lib.fv_max_eigenvalue.argtypes = [vp, i64, vp, i64, i32, i32, i32, i32, i32, f64, vp, vp, vp]
     lib.fv_max_eigenvalue.restype = i32
+    for base in ("fv_batch_update", "fv_batch_update_gather", "fv_step_gather",
+                 "fv_max_eigenvalue"):
+        f32 = getattr(lib, base + "_f32")
+        f32.argtypes = getattr(lib, base).argtypes
+        f32.restype = i32
+    for name in ("fv_conserved_totals", "fv_conserved_totals_f32"):
+        getattr(lib, name).argtypes = [vp, i64, vp, i64, i32, i32, i32, i32, i32, vp, vp, vp]
+        getattr(lib, name).restype = i32
     lib.fv_cfl_timestep.argtypes = [vp, i64, vp, i32, f64, vp, vp, vp]
     lib.fv_cfl_timestep.restype = i32
     lib.fv_fill_halo.argtypes = [vp, i64, vp, vp, i64, i32, i32, i32, i32, i32, vp]
@@ -100,6 +108,22 @@ def _dev_f64(t, name):
             and t.is_contiguous()):
         raise TypeError(f"{name} must be a contiguous float64 device tensor")
     return t
+
+
+def _dev_state(t, name):
+    """A solution buffer: float64 or float32; returns the entry-point suffix."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()
+            and t.dtype in (torch.float64, torch.float32)):
+        raise TypeError(f"{name} must be a contiguous float64 or float32 device tensor")
+    return "" if t.dtype == torch.float64 else "_f32"
+
+
+def _same_state(a, b):
+    sa, sb = _dev_state(a, "q_in"), _dev_state(b, "q_out")
+    if sa != sb:
+        raise TypeError("q_in and q_out must have the same dtype")
+    return sa
 
 
 def _n_patches(patches):
@@ -148,9 +172,8 @@ def upload_patches(desc, device="cuda", *, dim=None, p=None, q_out_halo=None, q_
 
 def batch_update(patches, q_in, q_out, *, dim, p, gamma=1.4, q_out_halo=True, dt=None,
                  max_eig=None, stream=None):
-    """fv_batch_update: one explicit Euler step of every patch (see include/fv.h)."""
-    _dev_f64(q_in, "q_in")
-    _dev_f64(q_out, "q_out")
+    """fv_batch_update[_f32]: one explicit Euler step of every patch (see include/fv.h)."""
+    sfx = _same_state(q_in, q_out)
     if max_eig is not None:
         _dev_f64(max_eig, "max_eig")
     if dt is not None:
@@ -158,9 +181,10 @@ def batch_update(patches, q_in, q_out, *, dim, p, gamma=1.4, q_out_halo=True, dt
     n = _n_patches(patches)
     if max_eig is not None and max_eig.numel() < n:
         raise ValueError("max_eig needs one entry per patch")
-    _check(library().fv_batch_update(_ptr(patches), n, _ptr(q_in), q_in.numel(), _ptr(q_out),
-                                     q_out.numel(), int(bool(q_out_halo)), dim, p, 1, dim + 2,
-                                     float(gamma), _ptr(dt), _ptr(max_eig), _stream(stream)))
+    fn = getattr(library(), "fv_batch_update" + sfx)
+    _check(fn(_ptr(patches), n, _ptr(q_in), q_in.numel(), _ptr(q_out), q_out.numel(),
+              int(bool(q_out_halo)), dim, p, 1, dim + 2, float(gamma), _ptr(dt), _ptr(max_eig),
+              _stream(stream)))
 
 
 def _dev_nbr(neighbours, n, dim):
@@ -174,9 +198,8 @@ def _dev_nbr(neighbours, n, dim):
 
 def batch_update_gather(patches, neighbours, q_in, q_out, *, dim, p, gamma=1.4,
                         q_out_halo=False, dt=None, max_eig=None, stream=None):
-    """fv_batch_update_gather: update with the face-halo exchange fused into the gather."""
-    _dev_f64(q_in, "q_in")
-    _dev_f64(q_out, "q_out")
+    """fv_batch_update_gather[_f32]: update with the face-halo exchange fused into the gather."""
+    sfx = _same_state(q_in, q_out)
     if max_eig is not None:
         _dev_f64(max_eig, "max_eig")
     if dt is not None:
@@ -185,10 +208,10 @@ def batch_update_gather(patches, neighbours, q_in, q_out, *, dim, p, gamma=1.4,
     _dev_nbr(neighbours, n, dim)
     if max_eig is not None and max_eig.numel() < n:
         raise ValueError("max_eig needs one entry per patch")
-    _check(library().fv_batch_update_gather(_ptr(patches), n, _ptr(neighbours), _ptr(q_in),
-                                            q_in.numel(), _ptr(q_out), q_out.numel(),
-                                            int(bool(q_out_halo)), dim, p, dim + 2, float(gamma),
-                                            _ptr(dt), _ptr(max_eig), _stream(stream)))
+    fn = getattr(library(), "fv_batch_update_gather" + sfx)
+    _check(fn(_ptr(patches), n, _ptr(neighbours), _ptr(q_in), q_in.numel(), _ptr(q_out),
+              q_out.numel(), int(bool(q_out_halo)), dim, p, dim + 2, float(gamma), _ptr(dt),
+              _ptr(max_eig), _stream(stream)))
 
 
 def step_workspace_words(n, dim, p):
@@ -198,10 +221,9 @@ def step_workspace_words(n, dim, p):
 
 def step_gather(patches, neighbours, q_in, q_out, dt, dt_next, workspace, *, dim, p, gamma=1.4,
                 cfl=0.4, max_eig=None, lambda_out=None, stream=None):
-    """fv_step_gather: update (halo exchange fused) + next CFL time step, one launch."""
+    """fv_step_gather[_f32]: update (halo exchange fused) + next CFL time step, one launch."""
     import torch
-    _dev_f64(q_in, "q_in")
-    _dev_f64(q_out, "q_out")
+    sfx = _same_state(q_in, q_out)
     _dev_f64(dt, "dt")
     _dev_f64(dt_next, "dt_next")
     for t, name in ((max_eig, "max_eig"), (lambda_out, "lambda_out")):
@@ -216,26 +238,41 @@ def step_gather(patches, neighbours, q_in, q_out, dt, dt_next, workspace, *, dim
     _dev_nbr(neighbours, n, dim)
     if max_eig is not None and max_eig.numel() < n:
         raise ValueError("max_eig needs one entry per patch")
-    _check(library().fv_step_gather(_ptr(patches), n, _ptr(neighbours), _ptr(q_in), q_in.numel(),
-                                    _ptr(q_out), q_out.numel(), dim, p, dim + 2, float(gamma),
-                                    float(cfl), _ptr(dt), _ptr(max_eig), _ptr(dt_next),
-                                    _ptr(lambda_out), _ptr(workspace), workspace.numel(),
-                                    _stream(stream)))
+    fn = getattr(library(), "fv_step_gather" + sfx)
+    _check(fn(_ptr(patches), n, _ptr(neighbours), _ptr(q_in), q_in.numel(), _ptr(q_out),
+              q_out.numel(), dim, p, dim + 2, float(gamma), float(cfl), _ptr(dt), _ptr(max_eig),
+              _ptr(dt_next), _ptr(lambda_out), _ptr(workspace), workspace.numel(),
+              _stream(stream)))
 
 
 def max_eigenvalue(patches, q, per_patch, global_out=None, *, dim, p, gamma=1.4, q_halo=True,
                    which=FV_OFFSETS_IN, stream=None):
-    """fv_max_eigenvalue: per-patch (and optionally global) largest eigenvalue of q."""
-    _dev_f64(q, "q")
+    """fv_max_eigenvalue[_f32]: per-patch (and optionally global) largest eigenvalue of q."""
+    sfx = _dev_state(q, "q")
     _dev_f64(per_patch, "per_patch")
     if global_out is not None:
         _dev_f64(global_out, "global_out")
     n = _n_patches(patches)
     if per_patch.numel() < n:
         raise ValueError("per_patch needs one entry per patch")
-    _check(library().fv_max_eigenvalue(_ptr(patches), n, _ptr(q), q.numel(), int(bool(q_halo)),
-                                       which, dim, p, dim + 2, float(gamma), _ptr(per_patch),
-                                       _ptr(global_out), _stream(stream)))
+    fn = getattr(library(), "fv_max_eigenvalue" + sfx)
+    _check(fn(_ptr(patches), n, _ptr(q), q.numel(), int(bool(q_halo)), which, dim, p, dim + 2,
+              float(gamma), _ptr(per_patch), _ptr(global_out), _stream(stream)))
+
+
+def conserved_totals(patches, q, per_patch, totals=None, *, dim, p, q_halo=True,
+                     which=FV_OFFSETS_IN, stream=None):
+    """fv_conserved_totals[_f32]: FP64 totals of the conserved unknowns (per patch, and summed)."""
+    sfx = _dev_state(q, "q")
+    _dev_f64(per_patch, "per_patch")
+    if totals is not None:
+        _dev_f64(totals, "totals")
+    n = _n_patches(patches)
+    if per_patch.numel() < n * (dim + 2):
+        raise ValueError("per_patch needs (dim+2) entries per patch")
+    _check(getattr(library(), "fv_conserved_totals" + sfx)(
+        _ptr(patches), n, _ptr(q), q.numel(), int(bool(q_halo)), which, dim, p, dim + 2,
+        _ptr(per_patch), _ptr(totals), _stream(stream)))
 
 
 def cfl_timestep(patches, per_patch, *, dim, cfl=0.4, lambda_out=None, dt_out=None,
@@ -274,14 +311,14 @@ class Stepper:
     """
 
     def __init__(self, desc, neighbours, q0, *, dim, p, gamma=1.4, cfl=0.4, mode="fused",
-                 device="cuda"):
+                 device="cuda", dtype=None):
         import torch
         if mode not in ("fused", "gather", "halo"):
             raise ValueError("mode must be 'fused', 'gather' or 'halo'")
         desc = np.ascontiguousarray(desc, dtype=PATCH_DTYPE)
         if not np.array_equal(desc["q_in"], desc["q_out"]):
             raise ValueError("the ping-pong stepper needs q_in == q_out offsets")
-        q0 = np.ascontiguousarray(q0, dtype=np.float64)
+        q0 = np.ascontiguousarray(q0, dtype=np.float64 if dtype is None else dtype)
         self.mode = mode
         self.halo = mode == "halo"
         self.dim, self.p, self.gamma, self.cfl = dim, p, gamma, cfl

@@ -1,0 +1,161 @@
+"""FP32 bulk arithmetic (FP32 state, flux and update; FP64 maxima, CFL and
+conserved totals) against the FP64 oracle.
+
+Bar: relative L2 and L-infinity error per unknown <= 1e-5 after 1, 10 and 100
+steps (L2: ||Q32 - Q64|| / ||Q64|| over the volumes of one unknown; L-inf:
+max |Q32 - Q64| / max |Q64|; an unknown that is identically zero takes the
+denominator of the whole state).  The errors are printed per result.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_09005_amd import fv
+from paper_2302_09005_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_errors(got, ref):
+    """(max over unknowns of relative L2, of relative L-inf)."""
+    s = ref.shape[0]
+    g = got.reshape(s, -1).astype(np.float64)
+    r = ref.reshape(s, -1)
+    all_l2, all_li = np.linalg.norm(r), np.abs(r).max()
+    l2, li = [], []
+    for k in range(s):
+        d2 = np.linalg.norm(r[k]) or all_l2
+        di = np.abs(r[k]).max() or all_li
+        l2.append(np.linalg.norm(g[k] - r[k]) / d2)
+        li.append(np.abs(g[k] - r[k]).max() / di)
+    return max(l2), max(li)
+
+
+def fp32_run(grid, q, steps):
+    import torch
+    st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
+                    grid.pack_compact(q), dim=grid.d, p=grid.p, mode="fused", dtype=np.float32)
+    out = {}
+    for i in range(1, steps + 1):
+        st.step()
+        if i in (1, 10, 100):
+            torch.cuda.synchronize()
+            out[i] = grid.unpack(st.state().cpu().numpy().astype(np.float64), halo=False)
+    return out, st
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    fv.library()
+
+
+def test_fp32_errors_at_1_10_100_steps():
+    grid, q = W.grid_3d_random_smooth(8, 8, seed=0)   # 512 patches of 8^3
+    got, _ = fp32_run(grid, q, 100)
+    flat = grid.pack(q)
+    a = flat
+    dx = np.full((grid.n, 3), grid.dx)
+    done = 0
+    for k in (1, 10, 100):
+        a, _, _ = oracle.run_steps(grid.offsets(), dx, a, grid.neighbours(), 3, 8, k - done)
+        done = k
+        l2, li = rel_errors(got[k], grid.unpack(a))
+        _say(f"[fp32 vs fp64 oracle, 512x8^3] step {k:3d}: rel L2 {l2:.2e}  rel Linf {li:.2e}")
+        assert l2 <= TOL32 and li <= TOL32
+
+
+def test_fp32_full_size_one_and_ten_steps():
+    grid, q = W.grid_3d_random_smooth(16, 8, seed=1)  # 4096 patches of 8^3
+    got, _ = fp32_run(grid, q, 10)
+    dx = np.full((grid.n, 3), grid.dx)
+    ref1, _, _ = oracle.run_steps(grid.offsets(), dx, grid.pack(q), grid.neighbours(), 3, 8, 1)
+    ref10, _, _ = oracle.run_steps(grid.offsets(), dx, ref1, grid.neighbours(), 3, 8, 9)
+    for k, ref in ((1, ref1), (10, ref10)):
+        l2, li = rel_errors(got[k], grid.unpack(ref))
+        _say(f"[fp32 vs fp64 oracle, 4096x8^3] step {k:3d}: rel L2 {l2:.2e}  rel Linf {li:.2e}")
+        assert l2 <= TOL32 and li <= TOL32
+
+
+@pytest.mark.parametrize("d,p,counts", [(2, 16, (8, 8)), (3, 4, (4, 4, 4)), (3, 16, (2, 2, 2)),
+                                        (2, 17, (3, 3))])
+def test_fp32_other_instances_one_step(d, p, counts):
+    import torch
+    rng = np.random.default_rng(p)
+    grid = W.PatchGrid(d, p, counts, 1.0 / (counts[0] * p))
+    q = W.to_conserved(rng.uniform(0.5, 1.5, grid.shape),
+                       [rng.uniform(-0.5, 0.5, grid.shape) for _ in range(d)],
+                       rng.uniform(0.5, 2.0, grid.shape))
+    per, _ = oracle.max_eigenvalue(grid.offsets(), grid.pack(q), d, p, True)
+    dt, _ = oracle.cfl_dt(np.full((grid.n, 3), grid.dx), per, d)
+    desc = grid.descriptors(dt=dt, out_halo=False)
+    ref, me_ref = oracle.fv_step(desc["q_in"], desc["q_out"], desc["dx"], desc["dt"],
+                                 grid.pack(q), d, p, out_halo=False,
+                                 out_len=grid.buffer_len(False))
+    qin = torch.from_numpy(grid.pack(q).astype(np.float32)).cuda()
+    qout = torch.zeros(grid.buffer_len(False), dtype=torch.float32, device="cuda")
+    me = torch.empty(grid.n, dtype=torch.float64, device="cuda")
+    fv.batch_update(fv.upload_patches(desc), qin, qout, dim=d, p=p, q_out_halo=False, max_eig=me)
+    torch.cuda.synchronize()
+    l2, li = rel_errors(grid.unpack(qout.cpu().numpy().astype(np.float64), halo=False),
+                        grid.unpack(ref, halo=False))
+    _say(f"[fp32 one step d={d} p={p}] rel L2 {l2:.2e} rel Linf {li:.2e}")
+    assert l2 <= TOL32 and li <= TOL32
+    np.testing.assert_allclose(me.cpu().numpy(), me_ref, rtol=1e-6)
+
+
+def test_fp64_totals_of_fp32_state_and_conservation():
+    """FP64 totals (fixed order) match an exactly rounded sum of the same FP32
+    values, and the FP32 periodic run conserves them to FP32 rounding."""
+    import torch
+    grid, q = W.grid_3d_random_smooth(8, 8, seed=3)
+    _, st = fp32_run(grid, q, 10)
+    desc = grid.descriptors(out_halo=False, in_halo=False)
+    pd = fv.upload_patches(desc)
+    per = torch.empty(grid.n * 5, dtype=torch.float64, device="cuda")
+    tot = torch.empty(5, dtype=torch.float64, device="cuda")
+    fv.conserved_totals(pd, st.state(), per, tot, dim=3, p=8, q_halo=False)
+    torch.cuda.synchronize()
+    state = grid.unpack(st.state().cpu().numpy().astype(np.float64), halo=False)
+    exact = [math.fsum(state[k].ravel()) for k in range(5)]
+    scale = [math.fsum(np.abs(state[k]).ravel()) for k in range(5)]
+    for k in range(5):
+        assert abs(tot[k].item() - exact[k]) <= 1e-13 * scale[k]
+    q32 = grid.unpack(grid.pack_compact(q).astype(np.float32).astype(np.float64), halo=False)
+    start = [math.fsum(q32[k].ravel()) for k in range(5)]
+    for k in range(5):
+        drift = abs(exact[k] - start[k]) / scale[k]
+        _say(f"[fp32 conservation, 10 steps] unknown {k}: relative drift {drift:.2e}")
+        assert drift <= 1e-6
+
+
+def test_fp64_totals_kernel_matches_oracle():
+    import torch
+    grid, q = W.grid_3d_random_smooth(4, 8, seed=4)
+    flat = grid.pack(q)
+    per = torch.empty(grid.n * 5, dtype=torch.float64, device="cuda")
+    tot = torch.empty(5, dtype=torch.float64, device="cuda")
+    fv.conserved_totals(fv.upload_patches(grid.descriptors()), torch.from_numpy(flat).cuda(), per,
+                        tot, dim=3, p=8, q_halo=True)
+    torch.cuda.synchronize()
+    ref = oracle.totals(grid.offsets(), flat, 3, 8, True)
+    # sums in a different order: compare within rounding of the sum of magnitudes
+    absq = np.abs(np.nan_to_num(flat))
+    scale = oracle.totals(grid.offsets(), absq, 3, 8, True)
+    assert (np.abs(tot.cpu().numpy() - ref) <= 1e-13 * scale).all()
+    per_ref = np.stack([oracle.totals(grid.offsets()[b:b + 1], flat, 3, 8, True)
+                        for b in range(grid.n)])
+    per_scale = np.stack([oracle.totals(grid.offsets()[b:b + 1], absq, 3, 8, True)
+                          for b in range(grid.n)])
+    got = per.cpu().numpy().reshape(grid.n, 5)
+    assert (np.abs(got - per_ref) <= 1e-13 * per_scale).all()
