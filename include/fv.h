@@ -242,6 +242,77 @@ int fv_conserved_totals_f32(const fv_patch* patches, int64_t n_patches,
                             void* stream);
 
 /*
+ * Uneven batches with local time stepping (3-D, patches of 4^3, 8^3 and 16^3
+ * volumes mixed in one batch; compact blocks; halo gathered from neighbours,
+ * which must have the same p).  The paper's engine offloads N patches at a
+ * time whatever their AMR level (Section 2, enclave tasking) and keeps a
+ * time step per patch (Section 4, local adaptive time stepping; App. A
+ * per-patch t and dt).
+ *
+ * A plan groups the patches by size: `order` lists the patch indices sorted
+ * by p (16, 8, 4; stable), and each work unit is a run of `order` of one size
+ * that fills one 256-thread workgroup (1 x 16^3, 4 x 8^3 or 16 x 4^3).
+ * fv_plan_mixed builds it on the host from a HOST copy of the descriptors;
+ * the caller uploads `order` and `units` and fills the device pointers.
+ */
+#define FV_SCHED_PER_SIZE   0   /* one launch per size class (batched loops)    */
+#define FV_SCHED_PERSISTENT 1   /* one persistent launch over all work units    */
+#define FV_SCHED_PATCHWISE  2   /* one launch per patch (the paper's patch-wise
+                                   loop order, Section 3; for comparison only)  */
+
+typedef struct fv_work_unit {
+  int32_t p;       /* volumes per axis of the unit's patches          */
+  int32_t count;   /* patches in the unit                             */
+  int64_t first;   /* position of its first patch in `order`          */
+} fv_work_unit;
+
+typedef struct fv_mixed_plan {
+  const int64_t* order;        /* device [n_patches]                                 */
+  const fv_work_unit* units;   /* device [n_units]                                   */
+  int64_t n_units;
+  int32_t class_p[3];          /* sizes present, descending; 0 = unused class        */
+  int64_t class_first[3];      /* first position in `order` of each class            */
+  int64_t class_count[3];      /* patches of each class                              */
+} fv_mixed_plan;
+
+/*
+ * Host: fill order[n_patches] and units[<= n_patches] (host arrays) and the
+ * class fields of *plan (its device pointers are left for the caller).
+ * Rejects p outside {4, 8, 16} and dim != 3.  Touches no device.
+ */
+int fv_plan_mixed(const fv_patch* host_patches, int64_t n_patches, int dim,
+                  int64_t* order, fv_work_unit* units, fv_mixed_plan* plan);
+
+/*
+ * One step of every patch of an uneven batch with local time stepping: each
+ * patch advances by its own descriptor dt (its t grows by dt) and stores its
+ * next CFL step, dt = cfl * min dx / (dim * lambda_patch), from its new
+ * state; max_eig (device [n_patches] or NULL) gets the per-patch maxima.
+ * patches is written (t and dt only).  schedule: one of FV_SCHED_*;
+ * persistent_workgroups: grid of the persistent launch (0 = one workgroup
+ * per unit).  Every schedule gives bit-identical results.  Other arguments as for
+ * fv_batch_update_gather with q_out compact.
+ */
+int fv_step_local(fv_patch* patches, int64_t n_patches, const int64_t* neighbours,
+                  const fv_mixed_plan* plan,
+                  const double* q_in, int64_t q_in_len, double* q_out, int64_t q_out_len,
+                  int dim, int s, double gamma, double cfl, double* max_eig,
+                  int schedule, int persistent_workgroups, void* stream);
+int fv_step_local_f32(fv_patch* patches, int64_t n_patches, const int64_t* neighbours,
+                      const fv_mixed_plan* plan,
+                      const float* q_in, int64_t q_in_len, float* q_out, int64_t q_out_len,
+                      int dim, int s, double gamma, double cfl, double* max_eig,
+                      int schedule, int persistent_workgroups, void* stream);
+
+/*
+ * Local time steps from per-patch maxima: patches[b].dt = cfl * min dx /
+ * (dim * per_patch[b]) for every patch (the first step of a run with local
+ * time stepping).  patches is written (dt only).
+ */
+int fv_local_timestep(fv_patch* patches, int64_t n_patches, const double* per_patch,
+                      int dim, double cfl, void* stream);
+
+/*
  * fv_max_eigenvalue -- largest eigenvalue of a given state (Section 2,
  * eq. (5); Algorithm 1 last step), for the first CFL step of a run.
  *

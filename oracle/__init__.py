@@ -48,6 +48,8 @@ def _load():
     lib.oracle_max_eigenvalue.restype = ctypes.c_int
     lib.oracle_cfl_dt.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]
     lib.oracle_cfl_dt.restype = ctypes.c_double
+    lib.oracle_local_dt.argtypes = [ctypes.c_int64, ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]
+    lib.oracle_local_dt.restype = None
     lib.oracle_fill_halo.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, _i64p, _i64p, _dp]
     lib.oracle_fill_halo.restype = ctypes.c_int
     lib.oracle_totals.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, _i64p,
@@ -155,6 +157,17 @@ def cfl_dt(dx, max_eig, d, cfl=0.4):
     return dt, lam.value
 
 
+def local_dt(dx, max_eig, d, cfl=0.4):
+    """Per-patch CFL steps dt[b] = cfl * min dx[b] / (d * max_eig[b]) (Section 4)."""
+    max_eig, mp = _f64(max_eig)
+    n = max_eig.shape[0]
+    dx = np.ascontiguousarray(np.broadcast_to(np.asarray(dx, np.float64), (n, 3)))
+    dx, dxp = _f64(dx)
+    dt = np.empty(n)
+    _load().oracle_local_dt(n, d, dxp, mp, cfl, dt.ctypes.data_as(_dp))
+    return dt
+
+
 def fill_halo(off, neighbours, q, d, p):
     """Face-halo fill in place (periodic via the neighbour table; -1 = transmissive)."""
     off, op = _i64(off)
@@ -213,3 +226,65 @@ def run_steps(q_in_off, dx, q, neighbours, d, p, steps, gamma=1.4, cfl=0.4,
         t += dt
         dts.append(dt)
     return a, t, dts
+
+
+def run_local_steps(off, sizes, dx, neighbours, q, steps, dt=None, t=None, gamma=1.4, cfl=0.4,
+                    nthreads=0):
+    """Local time stepping over a 3-D batch of mixed patch sizes (Section 4).
+
+    off, sizes: int64[n] offsets of compact blocks [5][p_b^3] in q and their
+    p_b; dx: float64[n, 3]; neighbours: int64[n, 6] (a neighbour must have the
+    same p; -1 = transmissive).  Each step, for every patch b: fill its face
+    halo, advance it by its own dt[b] (fv_step), t[b] += dt[b], then take
+    dt[b] = local_dt from the new state's maximum.  When dt is None the first
+    steps come from the initial state.  Patches of different size never
+    interact, so each size class runs as one halo'd batch.
+    Returns (q, dt, t, max_eig) after ``steps`` steps.
+    """
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+    n = off.shape[0]
+    dx = np.ascontiguousarray(np.broadcast_to(np.asarray(dx, np.float64), (n, 3)))
+    nbr = np.ascontiguousarray(neighbours, dtype=np.int64).reshape(n, 6)
+    q = np.array(q, dtype=np.float64, copy=True)
+    t = np.zeros(n) if t is None else np.array(t, dtype=np.float64, copy=True)
+    me = np.full(n, np.nan)
+    classes = []
+    for p in sorted(set(int(v) for v in sizes)):
+        idx = np.nonzero(sizes == p)[0]
+        pos = np.full(n, -1, dtype=np.int64)
+        pos[idx] = np.arange(idx.shape[0])
+        sub = nbr[idx]
+        if ((sub >= 0) & (sizes[np.maximum(sub, 0)] != p)).any():
+            raise ValueError("a neighbour has a different patch size")
+        local_nbr = np.where(sub >= 0, pos[np.maximum(sub, 0)], -1)
+        w = p + 2
+        hoff = np.arange(idx.shape[0], dtype=np.int64) * 5 * w ** 3
+        classes.append((p, idx, local_nbr, hoff))
+    if dt is None:
+        dt = np.empty(n)
+        for p, idx, _, _ in classes:
+            blocks = np.concatenate([q[off[b]:off[b] + 5 * p ** 3] for b in idx])
+            coff = np.arange(idx.shape[0], dtype=np.int64) * 5 * p ** 3
+            per, _ = max_eigenvalue(coff, blocks, 3, p, False, gamma)
+            dt[idx] = local_dt(dx[idx], per, 3, cfl)
+    else:
+        dt = np.array(dt, dtype=np.float64, copy=True)
+    for _ in range(steps):
+        for p, idx, local_nbr, hoff in classes:
+            w = p + 2
+            m = idx.shape[0]
+            a = np.full((m, 5, w, w, w), np.nan)
+            for j, b in enumerate(idx):
+                a[j, :, 1:-1, 1:-1, 1:-1] = q[off[b]:off[b] + 5 * p ** 3].reshape(5, p, p, p)
+            a = a.reshape(-1)
+            fill_halo(hoff, local_nbr, a, 3, p)
+            coff = np.arange(m, dtype=np.int64) * 5 * p ** 3
+            out, per = fv_step(hoff, coff, dx[idx], dt[idx], a, 3, p, gamma, out_halo=False,
+                               out_len=m * 5 * p ** 3, nthreads=nthreads)
+            for j, b in enumerate(idx):
+                q[off[b]:off[b] + 5 * p ** 3] = out[coff[j]:coff[j] + 5 * p ** 3]
+            t[idx] += dt[idx]
+            me[idx] = per
+            dt[idx] = local_dt(dx[idx], per, 3, cfl)
+    return q, dt, t, me

@@ -252,6 +252,21 @@ double oracle_cfl_dt(int64_t n, int d, const double* dx,
 }
 
 /*
+ * Local time stepping (Section 4; per-patch t and dt of the patch data in
+ * Appendix A): every patch takes its own step from its own maximum,
+ * dt[b] = cfl * (smallest dx of patch b) / (d * max_eig[b]), the CFL rule of
+ * oracle_cfl_dt applied to patch b alone.
+ */
+void oracle_local_dt(int64_t n, int d, const double* dx, const double* max_eig,
+                     double cfl, double* dt) {
+  for (int64_t b = 0; b < n; ++b) {
+    double h = INFINITY;
+    for (int j = 0; j < d; ++j) h = (dx[3 * b + j] < h) ? dx[3 * b + j] : h;
+    dt[b] = cfl * h / ((double)d * max_eig[b]);
+  }
+}
+
+/*
  * Face-halo fill (the engine's consistency step, Section 2).  For patch b and
  * face f = 2*axis + side (side 0: low, 1: high), nb = neighbours[2*d*b + f]:
  *   nb >= 0: the halo layer takes the neighbour's interior layer that touches

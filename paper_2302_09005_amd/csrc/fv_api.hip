@@ -244,6 +244,135 @@ int totals_impl(const char* name, const fv_patch* patches, int64_t n, const T* q
   return launched(name);
 }
 
+template <typename T>
+int step_local_impl(const char* name, fv_patch* patches, int64_t n, const int64_t* neighbours,
+                    const fv_mixed_plan* plan, const T* q_in, int64_t q_in_len, T* q_out,
+                    int64_t q_out_len, int dim, int s, double gamma, double cfl,
+                    double* max_eig, int schedule, int grid, void* stream) {
+  if (dim != 3) return fail(FV_EUNSUPPORTED, "uneven batches are 3-D only (got dim=%d)", dim);
+  if (s != dim + 2) return fail(FV_EINVAL, "s must be dim + 2 = %d (got %d)", dim + 2, s);
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (!(cfl > 0.0) || !isfinite(cfl)) return fail(FV_EINVAL, "cfl must be finite and > 0");
+  if (schedule != FV_SCHED_PER_SIZE && schedule != FV_SCHED_PERSISTENT &&
+      schedule != FV_SCHED_PATCHWISE)
+    return fail(FV_EINVAL, "schedule must be one of FV_SCHED_PER_SIZE, FV_SCHED_PERSISTENT, "
+                           "FV_SCHED_PATCHWISE (got %d)", schedule);
+  if (grid < 0) return fail(FV_EINVAL, "persistent_workgroups < 0");
+  if (!plan) return fail(FV_EINVAL, "null plan");
+  if (n == 0) return ok();
+  if (!patches || !neighbours || !q_in || !q_out || !plan->order || !plan->units)
+    return fail(FV_EINVAL, "null device pointer");
+  if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  int64_t next = 0, units = 0;
+  for (int c = 0; c < 3; ++c) {
+    const int64_t cnt = plan->class_count[c];
+    if (cnt == 0) continue;
+    const int pp = plan->class_p[c];
+    const int ppu = fvk::mixed_patches_per_unit(pp);
+    if (ppu == 0) return fail(FV_EUNSUPPORTED, "plan class %d: no instance for p=%d", c, pp);
+    if (cnt < 0 || plan->class_first[c] != next)
+      return fail(FV_EINVAL, "plan class %d does not continue the order at %lld", c,
+                  (long long)next);
+    next += cnt;
+    units += (cnt + ppu - 1) / ppu;
+  }
+  if (next != n) return fail(FV_EINVAL, "plan covers %lld patches, batch has %lld",
+                             (long long)next, (long long)n);
+  if (plan->n_units != units)
+    return fail(FV_EINVAL, "plan has %lld work units, its classes need %lld",
+                (long long)plan->n_units, (long long)units);
+  int rc = overlap_check(q_in, q_in_len, q_out, q_out_len);
+  if (rc) return rc;
+  rc = fvk::launch_step_local<T>(patches, n, neighbours, *plan, q_in, q_in_len, q_out, q_out_len,
+                                 gamma, cfl, max_eig, schedule, grid, (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance in the plan");
+  return launched(name);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fv_plan_mixed(const fv_patch* host_patches, int64_t n, int dim, int64_t* order,
+                  fv_work_unit* units, fv_mixed_plan* plan) {
+  if (dim != 3) return fail(FV_EUNSUPPORTED, "uneven batches are 3-D only (got dim=%d)", dim);
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (!plan) return fail(FV_EINVAL, "null plan");
+  if (n > 0 && (!host_patches || !order || !units)) return fail(FV_EINVAL, "null host pointer");
+  static const int sizes[3] = {16, 8, 4};  // biggest units first
+  int64_t count[3] = {0, 0, 0};
+  for (int64_t b = 0; b < n; ++b) {
+    const int pp = host_patches[b].p;
+    int c = 0;
+    while (c < 3 && sizes[c] != pp) ++c;
+    if (c == 3) return fail(FV_EUNSUPPORTED, "patch %lld: p=%d not in {4, 8, 16}",
+                            (long long)b, pp);
+    ++count[c];
+  }
+  int64_t pos[3];
+  int64_t first = 0, nu = 0;
+  for (int c = 0; c < 3; ++c) {
+    plan->class_p[c] = sizes[c];
+    plan->class_first[c] = first;
+    plan->class_count[c] = count[c];
+    pos[c] = first;
+    first += count[c];
+  }
+  for (int64_t b = 0; b < n; ++b) {  // stable counting sort by size class
+    const int pp = host_patches[b].p;
+    const int c = pp == 16 ? 0 : pp == 8 ? 1 : 2;
+    order[pos[c]++] = b;
+  }
+  for (int c = 0; c < 3; ++c) {
+    const int ppu = fvk::mixed_patches_per_unit(sizes[c]);
+    for (int64_t k = 0; k < count[c]; k += ppu) {
+      units[nu].p = sizes[c];
+      units[nu].count = (int32_t)std::min<int64_t>(ppu, count[c] - k);
+      units[nu].first = plan->class_first[c] + k;
+      ++nu;
+    }
+  }
+  plan->order = nullptr;
+  plan->units = nullptr;
+  plan->n_units = nu;
+  return ok();
+}
+
+int fv_step_local(fv_patch* patches, int64_t n, const int64_t* neighbours,
+                  const fv_mixed_plan* plan, const double* q_in, int64_t q_in_len, double* q_out,
+                  int64_t q_out_len, int dim, int s, double gamma, double cfl, double* max_eig,
+                  int schedule, int persistent_workgroups, void* stream) {
+  return step_local_impl<double>("fv_step_local", patches, n, neighbours, plan, q_in, q_in_len,
+                                 q_out, q_out_len, dim, s, gamma, cfl, max_eig, schedule,
+                                 persistent_workgroups, stream);
+}
+
+int fv_step_local_f32(fv_patch* patches, int64_t n, const int64_t* neighbours,
+                      const fv_mixed_plan* plan, const float* q_in, int64_t q_in_len,
+                      float* q_out, int64_t q_out_len, int dim, int s, double gamma, double cfl,
+                      double* max_eig, int schedule, int persistent_workgroups, void* stream) {
+  return step_local_impl<float>("fv_step_local_f32", patches, n, neighbours, plan, q_in,
+                                q_in_len, q_out, q_out_len, dim, s, gamma, cfl, max_eig,
+                                schedule, persistent_workgroups, stream);
+}
+
+int fv_local_timestep(fv_patch* patches, int64_t n, const double* per_patch, int dim, double cfl,
+                      void* stream) {
+  if (dim != 2 && dim != 3) return fail(FV_EINVAL, "dim must be 2 or 3");
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (!(cfl > 0.0) || !isfinite(cfl)) return fail(FV_EINVAL, "cfl must be finite and > 0");
+  if (n == 0) return ok();
+  if (!patches || !per_patch) return fail(FV_EINVAL, "null device pointer");
+  fvk::launch_local_dt(patches, n, per_patch, dim, cfl, (hipStream_t)stream);
+  return launched("fv_local_timestep");
+}
+
+}  // extern "C"
+
+namespace {
+
 }  // namespace
 
 extern "C" {

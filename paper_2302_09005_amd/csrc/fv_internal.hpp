@@ -16,8 +16,10 @@ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 //
 // The update walks the last axis (z in 3-D, y in 2-D): one lane owns one
 // column of volumes along that axis, so a patch occupies P^(D-1) lanes
-// ("LANES") and PPW patches share one workgroup when LANES < 64.
-template <int D, int P>
+// ("LANES") and PPW patches share one workgroup of NTW threads when
+// LANES < NTW (NTW = 64 for the single-size kernels, 256 in the mixed-size
+// persistent kernel).
+template <int D, int P, int NTW = 64>
 struct Geo {
   static constexpr int S = D + 2;                    // unknowns
   static constexpr int W = P + 2;                    // volumes per axis incl. halo
@@ -26,7 +28,7 @@ struct Geo {
   static constexpr int SM = ipow(W, D - 1);          // halo'd stride of the marching axis
   static constexpr int SMO = ipow(P, D - 1);         // compact stride of the marching axis
   static constexpr int LANES = ipow(P, D - 1);       // lanes per patch (one column each)
-  static constexpr int PPW = LANES >= 64 ? 1 : 64 / LANES;  // patches per workgroup
+  static constexpr int PPW = LANES >= NTW ? 1 : NTW / LANES;  // patches per workgroup
   static constexpr int NT = ((PPW * LANES + 63) / 64) * 64; // workgroup size
   static constexpr int RING = D == 3 ? 4 * P : 2;    // face-halo volumes around one plane
   static constexpr int NEXTRA = D == 3 ? 2 * P : 1;  // in-plane faces on the high boundary
@@ -68,6 +70,15 @@ struct LaunchEvents {
 };
 LaunchEvents& launch_events();
 
+// Time-step handling of an update launch.
+enum StepMode : int {
+  kPlain = 0,      // dt from dt_dev or the descriptor; nothing else
+  kGlobalCfl = 1,  // plus the next global CFL step (fv_step_gather)
+  kLocalDt = 2,    // per-patch dt from the descriptor; the launch advances the
+                   // descriptor's t by it and stores the patch's next local
+                   // CFL step in its dt (local time stepping)
+};
+
 // Status for launchers: 0 ok, FV_EUNSUPPORTED when (dim, p) has no instance.
 // Update launchers, instantiated for double and float state.
 template <typename T>
@@ -85,6 +96,15 @@ int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighb
                        double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
                        hipStream_t st);
 
+// Uneven batches (3-D, p in {4, 8, 16}): patches per 256-thread work unit,
+// and one step with local time stepping under the given schedule.
+int mixed_patches_per_unit(int p);
+template <typename T>
+int launch_step_local(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                      const fv_mixed_plan& plan, const T* qin, int64_t qin_len, T* qout,
+                      int64_t qout_len, double gamma, double cfl, double* max_eig, int schedule,
+                      int grid, hipStream_t st);
+
 template <typename T>
 int launch_patch_max(const fv_patch* patches, int64_t n, const T* q, int64_t q_len, int q_halo,
                      int which, int dim, int p, double gamma, double* per_patch, hipStream_t st);
@@ -95,6 +115,9 @@ int launch_totals(const fv_patch* patches, int64_t n, const T* q, int64_t q_len,
 
 int launch_reduce_cfl(const fv_patch* patches, int64_t n, const double* per_patch, int dim,
                       double cfl, double* lambda_out, double* dt_out, hipStream_t st);
+
+int launch_local_dt(fv_patch* patches, int64_t n, const double* per_patch, int dim, double cfl,
+                    hipStream_t st);
 
 int launch_fill_halo_f64(const fv_patch* patches, int64_t n, const int64_t* neighbours,
                          double* q, int64_t q_len, int which, int dim, int p, hipStream_t st);

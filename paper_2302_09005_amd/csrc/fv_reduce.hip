@@ -193,7 +193,27 @@ void launch_tot(const fv_patch* patches, int64_t n, const T* q, int64_t q_len, i
                      patches, n, q, q_len, q_halo, which, per_patch);
 }
 
+// Local time steps: one thread per patch, dt = cfl * min dx / (dim * lambda).
+__global__ void __launch_bounds__(256)
+local_dt_kernel(fv_patch* __restrict__ patches, int64_t n, const double* __restrict__ per_patch,
+                int dim, double cfl) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= n) return;
+  double h = patches[b].dx[0];
+  for (int j = 1; j < dim; ++j) h = fmin(h, patches[b].dx[j]);
+  patches[b].dt = cfl * h / ((double)dim * per_patch[b]);
+}
+
 }  // namespace
+
+int launch_local_dt(fv_patch* patches, int64_t n, const double* per_patch, int dim, double cfl,
+                    hipStream_t st) {
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks == 0) return 0;
+  hipLaunchKernelGGL(local_dt_kernel, dim3((unsigned)blocks), dim3(256), 0, st, patches, n,
+                     per_patch, dim, cfl);
+  return 0;
+}
 
 template <typename T>
 int launch_patch_max(const fv_patch* patches, int64_t n, const T* q, int64_t q_len, int q_halo,

@@ -49,15 +49,26 @@ namespace {
 // positive and decreases as h grows, so an integer max of it is a min of h.
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
 
-template <typename T, int D, int P, bool GATHER, bool CFL>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, Geo<D, P>::NT)))
-fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
-                 const int64_t* __restrict__ neighbours,
-                 const T* __restrict__ qin, int64_t qin_len,
-                 T* __restrict__ qout, int64_t qout_len, int out_halo, T gamma,
-                 const double* __restrict__ dt_dev, double* __restrict__ max_eig,
-                 CflOut cflo) {
-  using G = Geo<D, P>;
+// Per-workgroup outputs of the update body for the caller's epilogue.
+struct BodyOut {
+  double lam;    // maximum of the new state of this thread's patch (NaN if skipped)
+  double hmin;   // smallest volume width of that patch
+  bool in_range; // this thread's slot holds a patch
+  int slot;      // slot of this thread in the workgroup
+  int l;         // lane within the slot
+};
+
+// The update of the (up to PPW) patches of one workgroup of NTW threads.
+// b: the patch of this thread's slot (-1: none).  lds: PPW * SLOT elements,
+// red: NT / 64 elements, both shared.  MODE: see StepMode (kLocalDt needs a
+// writable descriptor array and cfl).
+template <typename T, int D, int P, int NTW, bool GATHER, int MODE>
+__device__ __forceinline__ BodyOut update_body(
+    const fv_patch* __restrict__ patches, int64_t n, const int64_t* __restrict__ neighbours,
+    const T* __restrict__ qin, int64_t qin_len, T* __restrict__ qout, int64_t qout_len,
+    int out_halo, T gamma, const double* __restrict__ dt_dev, double* __restrict__ max_eig,
+    double cfl, int64_t b, T* __restrict__ lds, T* __restrict__ red) {
+  using G = Geo<D, P, NTW>;
   constexpr int S = G::S;
   constexpr int K = D - 1;  // marching axis
   constexpr int W = G::W;
@@ -68,14 +79,10 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   constexpr int CS = GATHER ? G::VOUT : G::VIN;
   constexpr int PS = GATHER ? G::SMO : G::SM;
 
-  __shared__ T lds[G::PPW * G::SLOT];
-  __shared__ T red[G::NT / 64];
-
   const int tid = threadIdx.x;
   const int slot = G::PPW == 1 ? 0 : tid / LANES;
   const int l = G::PPW == 1 ? tid : tid - slot * LANES;
-  const int64_t b = (int64_t)blockIdx.x * G::PPW + slot;
-  const bool in_range = (G::PPW == 1 || slot < G::PPW) && (b < n);
+  const bool in_range = (G::PPW == 1 || slot < G::PPW) && b >= 0 && b < n;
   const int x = l % P;
   const int y = (D == 3) ? l / P : 0;
   const bool has_ring = l < G::RING;
@@ -91,6 +98,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   int64_t lo_base = 0, hi_base = 0, ring_src = 0;  // element offsets (GATHER)
   T r[3] = {T(0), T(0), T(0)};
   double hmin = __builtin_inf();
+  double dt_used = 0.0, t_used = 0.0;
   bool ok = false;
   if (in_range) {
     const fv_patch pd = patches[b];
@@ -98,7 +106,9 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
     off_out = pd.q_out;
     ok = pd.p == P && off_in >= 0 && off_in <= qin_len - blk_in && off_out >= 0 &&
          off_out <= qout_len - blk_out;
-    const double dt = dt_dev ? *dt_dev : pd.dt;
+    const double dt = (MODE != kLocalDt && dt_dev) ? *dt_dev : pd.dt;
+    dt_used = dt;
+    t_used = pd.t;
 #pragma unroll
     for (int j = 0; j < D; ++j) r[j] = T(dt / pd.dx[j]);
     hmin = pd.dx[0];
@@ -388,8 +398,46 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   }
   const double lam_b = ok ? double(lam) : __builtin_nan("");
   if (in_range && l == 0 && max_eig) max_eig[b] = lam_b;
+  if constexpr (MODE == kLocalDt) {
+    // local time stepping: this patch moves to t + dt and takes its own
+    // next CFL step from the new state
+    if (in_range && l == 0 && ok) {
+      fv_patch* pw = const_cast<fv_patch*>(patches) + b;
+      pw->t = t_used + dt_used;
+      pw->dt = cfl * hmin / ((double)D * lam_b);
+    }
+  }
+  return BodyOut{lam_b, hmin, in_range, slot, l};
 
-  if constexpr (CFL) {
+}
+
+template <typename T, int D, int P, bool GATHER, int MODE>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, Geo<D, P>::NT)))
+fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
+                 const int64_t* __restrict__ neighbours,
+                 const T* __restrict__ qin, int64_t qin_len,
+                 T* __restrict__ qout, int64_t qout_len, int out_halo, T gamma,
+                 const double* __restrict__ dt_dev, double* __restrict__ max_eig,
+                 CflOut cflo, const int64_t* __restrict__ order, int64_t order_base,
+                 int64_t count) {
+  using G = Geo<D, P>;
+  __shared__ T lds[G::PPW * G::SLOT];
+  __shared__ T red[G::NT / 64];
+  const int tid = threadIdx.x;
+  const int slot = G::PPW == 1 ? 0 : tid / G::LANES;
+  // the patch of this thread's slot: launch item i is patch i, or the
+  // patch order[order_base + i] when the launch covers a sorted range
+  const int64_t i = (int64_t)blockIdx.x * G::PPW + slot;
+  int64_t b = -1;
+  if (slot < G::PPW && i < count) b = order ? order[order_base + i] : i;
+  const BodyOut bo = update_body<T, D, P, 64, GATHER, MODE == kLocalDt ? kLocalDt : kPlain>(
+      patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo, gamma, dt_dev, max_eig,
+      cflo.cfl, b, lds, red);
+  const double lam_b = bo.lam;
+  const double hmin = bo.hmin;
+  const bool in_range = bo.in_range;
+  const int l = bo.l;
+  if constexpr (MODE == kGlobalCfl) {
     // Fused CFL step.  Patch maxima and smallest volume widths are folded
     // with device-scope atomic maxima of IEEE bit patterns (values >= 0 or
     // NaN, so integer order is numeric order with NaN on top, and the result
@@ -424,8 +472,8 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
     if (tid == 0) {
       unsigned long long dep = 0;
 #pragma unroll
-      for (int i = 0; i < G::PPW; ++i)
-        if ((int64_t)blockIdx.x * G::PPW + i < n) dep |= dep_s[i];
+      for (int k = 0; k < G::PPW; ++k)
+        if ((int64_t)blockIdx.x * G::PPW + k < count) dep |= dep_s[k];
       const unsigned long long before =
           __hip_atomic_fetch_add(&gs[0], 1ull + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       stage = before == gsize - 1 ? 1 : 0;
@@ -459,31 +507,87 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   }
 }
 
-template <typename T, int D, int P, bool GATHER, bool CFL>
+// ---------------------------------------------------------------------------
+// Uneven batches: one persistent launch over a size-sorted list of work units.
+// A unit fills one 256-thread workgroup with patches of one size (one 16^3,
+// four 8^3 or sixteen 4^3 patches); workgroups take units round-robin
+// (unit u -> workgroup u mod gridDim.x), biggest units first, so the launch
+// needs no atomics and its schedule is fixed.  Every patch takes its own
+// time step (local time stepping, kLocalDt).
+// ---------------------------------------------------------------------------
+constexpr int kMixedNT = 256;
+template <int P>
+constexpr int mixed_lds() { return Geo<3, P, kMixedNT>::PPW * Geo<3, P, kMixedNT>::SLOT; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// Two waves per SIMD: the union of the three bodies would otherwise take
+// every register and leave one.
+template <typename T>
+__global__ void __launch_bounds__(kMixedNT) __attribute__((amdgpu_waves_per_eu(2)))
+fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
+                const int64_t* __restrict__ neighbours, const T* __restrict__ qin,
+                int64_t qin_len, T* __restrict__ qout, int64_t qout_len, T gamma, double cfl,
+                double* __restrict__ max_eig, const int64_t* __restrict__ order,
+                const fv_work_unit* __restrict__ units, int64_t n_units) {
+  __shared__ T lds[cmax(mixed_lds<16>(), cmax(mixed_lds<8>(), mixed_lds<4>()))];
+  __shared__ T red[kMixedNT / 64];
+  const int tid = threadIdx.x;
+  for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    const fv_work_unit un = units[u];
+    // a unit whose run leaves the order array is skipped (the host plan
+    // never makes one)
+    if (un.first < 0 || un.count < 0 || un.first > n - un.count) continue;
+    if (un.p == 16) {
+      const int64_t b = un.count > 0 ? order[un.first] : -1;
+      update_body<T, 3, 16, kMixedNT, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
+                                                      qout_len, 0, gamma, nullptr, max_eig, cfl,
+                                                      b, lds, red);
+    } else if (un.p == 8) {
+      const int slot = tid / 64;
+      const int64_t b = slot < un.count ? order[un.first + slot] : -1;
+      update_body<T, 3, 8, kMixedNT, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
+                                                     qout_len, 0, gamma, nullptr, max_eig, cfl,
+                                                     b, lds, red);
+    } else if (un.p == 4) {
+      const int slot = tid / 16;
+      const int64_t b = slot < un.count ? order[un.first + slot] : -1;
+      update_body<T, 3, 4, kMixedNT, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
+                                                     qout_len, 0, gamma, nullptr, max_eig, cfl,
+                                                     b, lds, red);
+    }
+    __syncthreads();  // the next unit reuses the LDS
+  }
+}
+
+template <typename T, int D, int P, bool GATHER, int MODE>
 int launch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin, int64_t qin_len,
            T* qout, int64_t qout_len, int out_halo, T gamma, const double* dt_dev,
-           double* max_eig, const CflOut& cflo, hipStream_t st) {
+           double* max_eig, const CflOut& cflo, const int64_t* order, int64_t order_base,
+           int64_t count, hipStream_t st) {
   using G = Geo<D, P>;
   static_assert(G::PPW * G::LANES <= G::NT, "workgroup too small");
-  const int64_t blocks = (n + G::PPW - 1) / G::PPW;
+  const int64_t blocks = (count + G::PPW - 1) / G::PPW;
+  if (blocks == 0) return 0;
   const LaunchEvents& ev = launch_events();
   // with caller events the dispatch packet itself records them, so they time
   // the kernel's execution and nothing around it
-  hipExtLaunchKernelGGL((fv_update_kernel<T, D, P, GATHER, CFL>), dim3((unsigned)blocks),
+  hipExtLaunchKernelGGL((fv_update_kernel<T, D, P, GATHER, MODE>), dim3((unsigned)blocks),
                         dim3(G::NT), 0, st, ev.start, ev.stop, 0, patches, n, nbr, qin, qin_len,
-                        qout, qout_len, out_halo, gamma, dt_dev, max_eig, cflo);
+                        qout, qout_len, out_halo, gamma, dt_dev, max_eig, cflo, order,
+                        order_base, count);
   return 0;
 }
 
-template <typename T, bool GATHER, bool CFL>
+template <typename T, bool GATHER, int MODE>
 int dispatch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin,
              int64_t qin_len, T* qout, int64_t qout_len, int out_halo, int dim, int p,
              double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
-             hipStream_t st) {
-#define FV_CASE(DD, PP)                                                                   \
-  if (dim == DD && p == PP)                                                               \
-    return launch<T, DD, PP, GATHER, CFL>(patches, n, nbr, qin, qin_len, qout, qout_len,  \
-                                          out_halo, T(gamma), dt_dev, max_eig, cflo, st);
+             const int64_t* order, int64_t order_base, int64_t count, hipStream_t st) {
+#define FV_CASE(DD, PP)                                                                     \
+  if (dim == DD && p == PP)                                                                 \
+    return launch<T, DD, PP, GATHER, MODE>(patches, n, nbr, qin, qin_len, qout, qout_len,   \
+                                           out_halo, T(gamma), dt_dev, max_eig, cflo, order, \
+                                           order_base, count, st);
   FV_CASE(2, 4)
   FV_CASE(2, 8)
   FV_CASE(2, 16)
@@ -523,8 +627,8 @@ template <typename T>
 int launch_update(const fv_patch* patches, int64_t n, const T* qin, int64_t qin_len, T* qout,
                   int64_t qout_len, int out_halo, int dim, int p, double gamma,
                   const double* dt_dev, double* max_eig, hipStream_t st) {
-  return dispatch<T, false, false>(patches, n, nullptr, qin, qin_len, qout, qout_len, out_halo,
-                                   dim, p, gamma, dt_dev, max_eig, CflOut{}, st);
+  return dispatch<T, false, kPlain>(patches, n, nullptr, qin, qin_len, qout, qout_len, out_halo,
+                                    dim, p, gamma, dt_dev, max_eig, CflOut{}, nullptr, 0, n, st);
 }
 
 template <typename T>
@@ -532,8 +636,9 @@ int launch_update_gather(const fv_patch* patches, int64_t n, const int64_t* neig
                          const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int out_halo,
                          int dim, int p, double gamma, const double* dt_dev, double* max_eig,
                          hipStream_t st) {
-  return dispatch<T, true, false>(patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo,
-                                  dim, p, gamma, dt_dev, max_eig, CflOut{}, st);
+  return dispatch<T, true, kPlain>(patches, n, neighbours, qin, qin_len, qout, qout_len,
+                                   out_halo, dim, p, gamma, dt_dev, max_eig, CflOut{}, nullptr, 0,
+                                   n, st);
 }
 
 template <typename T>
@@ -541,8 +646,55 @@ int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighb
                        const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int dim, int p,
                        double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
                        hipStream_t st) {
-  return dispatch<T, true, true>(patches, n, neighbours, qin, qin_len, qout, qout_len, 0, dim, p,
-                                 gamma, dt_dev, max_eig, cflo, st);
+  return dispatch<T, true, kGlobalCfl>(patches, n, neighbours, qin, qin_len, qout, qout_len, 0,
+                                       dim, p, gamma, dt_dev, max_eig, cflo, nullptr, 0, n, st);
+}
+
+int mixed_patches_per_unit(int p) {
+  return p == 16 ? Geo<3, 16, kMixedNT>::PPW
+       : p == 8  ? Geo<3, 8, kMixedNT>::PPW
+       : p == 4  ? Geo<3, 4, kMixedNT>::PPW
+                 : 0;
+}
+
+template <typename T>
+int launch_step_local(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                      const fv_mixed_plan& plan, const T* qin, int64_t qin_len, T* qout,
+                      int64_t qout_len, double gamma, double cfl, double* max_eig, int schedule,
+                      int grid, hipStream_t st) {
+  const LaunchEvents& ev = launch_events();
+  if (schedule == FV_SCHED_PERSISTENT) {
+    int64_t g = grid > 0 ? grid : plan.n_units;
+    if (g > plan.n_units) g = plan.n_units;
+    if (g < 1) return 0;
+    hipExtLaunchKernelGGL((fv_mixed_kernel<T>), dim3((unsigned)g), dim3(kMixedNT), 0, st,
+                          ev.start, ev.stop, 0, patches, n, neighbours, qin, qin_len, qout,
+                          qout_len, T(gamma), cfl, max_eig, plan.order, plan.units, plan.n_units);
+    return 0;
+  }
+  // per size: one launch over each class's contiguous range of the sorted
+  // order; patch-wise: one launch per patch
+  CflOut co;
+  co.cfl = cfl;
+  for (int c = 0; c < 3; ++c) {
+    const int64_t first = plan.class_first[c], count = plan.class_count[c];
+    if (count <= 0) continue;
+    const int64_t per = schedule == FV_SCHED_PATCHWISE ? 1 : count;
+    for (int64_t k = 0; k < count; k += per) {
+      int rc = FV_EUNSUPPORTED;
+#define FV_CLASS(PP)                                                                          \
+  if (plan.class_p[c] == PP)                                                                  \
+    rc = launch<T, 3, PP, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,          \
+                                          qout_len, 0, T(gamma), nullptr, max_eig, co,         \
+                                          plan.order, first + k, per, st);
+      FV_CLASS(4)
+      FV_CLASS(8)
+      FV_CLASS(16)
+#undef FV_CLASS
+      if (rc) return rc;
+    }
+  }
+  return 0;
 }
 
 #define FV_INSTANTIATE(T)                                                                     \
@@ -553,7 +705,10 @@ int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighb
                                        const double*, double*, hipStream_t);                    \
   template int launch_step_gather<T>(const fv_patch*, int64_t, const int64_t*, const T*,        \
                                      int64_t, T*, int64_t, int, int, double, const double*,     \
-                                     double*, const CflOut&, hipStream_t);
+                                     double*, const CflOut&, hipStream_t);                      \
+  template int launch_step_local<T>(const fv_patch*, int64_t, const int64_t*,                   \
+                                    const fv_mixed_plan&, const T*, int64_t, T*, int64_t,       \
+                                    double, double, double*, int, int, hipStream_t);
 FV_INSTANTIATE(double)
 FV_INSTANTIATE(float)
 #undef FV_INSTANTIATE

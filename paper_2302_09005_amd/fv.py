@@ -26,6 +26,23 @@ FV_EUNSUPPORTED = -2
 FV_EHIP = -3
 FV_OFFSETS_IN = 0
 FV_OFFSETS_OUT = 1
+FV_SCHED_PER_SIZE = 0
+FV_SCHED_PERSISTENT = 1
+FV_SCHED_PATCHWISE = 2
+SCHEDULES = {"per_size": FV_SCHED_PER_SIZE, "persistent": FV_SCHED_PERSISTENT,
+             "patchwise": FV_SCHED_PATCHWISE}
+
+
+class WorkUnit(ctypes.Structure):
+    """fv_work_unit (include/fv.h)."""
+    _fields_ = [("p", ctypes.c_int32), ("count", ctypes.c_int32), ("first", ctypes.c_int64)]
+
+
+class MixedPlan(ctypes.Structure):
+    """fv_mixed_plan (include/fv.h)."""
+    _fields_ = [("order", ctypes.c_void_p), ("units", ctypes.c_void_p),
+                ("n_units", ctypes.c_int64), ("class_p", ctypes.c_int32 * 3),
+                ("class_first", ctypes.c_int64 * 3), ("class_count", ctypes.c_int64 * 3)]
 
 _lib = None
 
@@ -79,6 +96,14 @@ def library():
     for name in ("fv_conserved_totals", "fv_conserved_totals_f32"):
         getattr(lib, name).argtypes = [vp, i64, vp, i64, i32, i32, i32, i32, i32, vp, vp, vp]
         getattr(lib, name).restype = i32
+    lib.fv_plan_mixed.argtypes = [vp, i64, i32, vp, vp, ctypes.POINTER(MixedPlan)]
+    lib.fv_plan_mixed.restype = i32
+    for name in ("fv_step_local", "fv_step_local_f32"):
+        getattr(lib, name).argtypes = [vp, i64, vp, ctypes.POINTER(MixedPlan), vp, i64, vp, i64,
+                                       i32, i32, f64, f64, vp, i32, i32, vp]
+        getattr(lib, name).restype = i32
+    lib.fv_local_timestep.argtypes = [vp, i64, vp, i32, f64, vp]
+    lib.fv_local_timestep.restype = i32
     lib.fv_cfl_timestep.argtypes = [vp, i64, vp, i32, f64, vp, vp, vp]
     lib.fv_cfl_timestep.restype = i32
     lib.fv_fill_halo.argtypes = [vp, i64, vp, vp, i64, i32, i32, i32, i32, i32, vp]
@@ -294,6 +319,134 @@ def fill_halo(patches, neighbours, q, *, dim, p, which=FV_OFFSETS_IN, stream=Non
     _dev_nbr(neighbours, n, dim)
     _check(library().fv_fill_halo(_ptr(patches), n, _ptr(neighbours), _ptr(q), q.numel(), which,
                                   dim, p, 1, dim + 2, _stream(stream)))
+
+
+class Plan:
+    """A work plan for an uneven batch (fv_plan_mixed), with its order and
+    work units uploaded to the device.  ``order`` (host) lists the patch
+    indices sorted by size, 16^3 first; ``units`` (host) is the work list."""
+
+    def __init__(self, desc, device="cuda", dim=3):
+        import torch
+        desc = np.ascontiguousarray(desc, dtype=PATCH_DTYPE)
+        n = desc.shape[0]
+        self.order = np.zeros(max(n, 1), dtype=np.int64)
+        self.units = (WorkUnit * max(n, 1))()
+        self.c = MixedPlan()
+        _check(library().fv_plan_mixed(desc.ctypes.data_as(ctypes.c_void_p), n, dim,
+                                       self.order.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.cast(self.units, ctypes.c_void_p),
+                                       ctypes.byref(self.c)))
+        self.order = self.order[:n]
+        nu = self.c.n_units
+        raw = np.frombuffer(bytes(self.units), dtype=np.uint8)[:nu * ctypes.sizeof(WorkUnit)]
+        self.units_host = raw.view(np.dtype([("p", "<i4"), ("count", "<i4"), ("first", "<i8")]))
+        self.order_dev = torch.from_numpy(self.order.copy()).to(device)
+        self.units_dev = torch.from_numpy(raw.copy()).to(device)
+        self.c.order = self.order_dev.data_ptr() if n else None
+        self.c.units = self.units_dev.data_ptr() if nu else None
+        self.n = n
+
+    @property
+    def n_units(self):
+        return int(self.c.n_units)
+
+    def classes(self):
+        """[(p, first, count)] of the size classes present, in plan order."""
+        return [(int(self.c.class_p[k]), int(self.c.class_first[k]), int(self.c.class_count[k]))
+                for k in range(3) if self.c.class_count[k] > 0]
+
+
+def step_local(patches, neighbours, plan, q_in, q_out, *, dim=3, gamma=1.4, cfl=0.4,
+               max_eig=None, schedule="persistent", workgroups=0, stream=None):
+    """fv_step_local[_f32]: one step of an uneven batch with local time steps
+    (each patch advances by its own descriptor dt; t and dt are updated)."""
+    sfx = _same_state(q_in, q_out)
+    if max_eig is not None:
+        _dev_f64(max_eig, "max_eig")
+    n = _n_patches(patches)
+    _dev_nbr(neighbours, n, dim)
+    if max_eig is not None and max_eig.numel() < n:
+        raise ValueError("max_eig needs one entry per patch")
+    if schedule not in SCHEDULES:
+        raise ValueError(f"schedule must be one of {sorted(SCHEDULES)}")
+    fn = getattr(library(), "fv_step_local" + sfx)
+    _check(fn(_ptr(patches), n, _ptr(neighbours), ctypes.byref(plan.c), _ptr(q_in), q_in.numel(),
+              _ptr(q_out), q_out.numel(), dim, dim + 2, float(gamma), float(cfl), _ptr(max_eig),
+              SCHEDULES[schedule], int(workgroups), _stream(stream)))
+
+
+def local_timestep(patches, per_patch, *, dim, cfl=0.4, stream=None):
+    """fv_local_timestep: patches[b].dt = cfl * min dx_b / (dim * per_patch[b])."""
+    _dev_f64(per_patch, "per_patch")
+    n = _n_patches(patches)
+    if per_patch.numel() < n:
+        raise ValueError("per_patch needs one entry per patch")
+    _check(library().fv_local_timestep(_ptr(patches), n, _ptr(per_patch), dim, float(cfl),
+                                       _stream(stream)))
+
+
+class LocalStepper:
+    """Device-resident driver for an uneven 3-D batch with local time steps.
+
+    The descriptors are stored on the device in plan order (16^3, then 8^3,
+    then 4^3 patches), with the neighbour table renumbered to match, so each
+    size class is one contiguous range; the state buffers keep the caller's
+    layout.  The first local steps come from the initial state (per class
+    fv_max_eigenvalue, then fv_local_timestep); each step is fv_step_local
+    under the chosen schedule, and swaps the state buffers.
+    """
+
+    def __init__(self, desc, neighbours, q0, *, gamma=1.4, cfl=0.4, schedule="persistent",
+                 workgroups=0, device="cuda", dtype=None):
+        import torch
+        desc = np.ascontiguousarray(desc, dtype=PATCH_DTYPE)
+        n = desc.shape[0]
+        q0 = np.ascontiguousarray(q0, dtype=np.float64 if dtype is None else dtype)
+        self.gamma, self.cfl = gamma, cfl
+        self.schedule, self.workgroups = schedule, workgroups
+        base = Plan(desc, device)
+        self.perm = base.order                         # device position -> patch
+        self.inv = np.empty(n, dtype=np.int64)
+        self.inv[self.perm] = np.arange(n)
+        sdesc = desc[self.perm]
+        nbr = np.ascontiguousarray(neighbours, np.int64).reshape(n, 6)[self.perm]
+        nbr = np.where(nbr >= 0, self.inv[np.maximum(nbr, 0)], nbr)
+        self.plan = Plan(sdesc, device)                # order is the identity now
+        self.n = n
+        for p, first, count in self.plan.classes():
+            check_patches(sdesc[first:first + count], 3, p, False, q0.size, q0.size,
+                          q_in_halo=False)
+        self.patches = upload_patches(sdesc, device)
+        self.neighbours = torch.from_numpy(np.ascontiguousarray(nbr)).to(device)
+        self.a = torch.from_numpy(q0).to(device)
+        self.b = self.a.clone()
+        self.per_patch = torch.empty(max(n, 1), dtype=torch.float64, device=device)
+        rec = PATCH_DTYPE.itemsize
+        for p, first, count in self.plan.classes():
+            max_eigenvalue(self.patches[first * rec:(first + count) * rec], self.a,
+                           self.per_patch[first:first + count], dim=3, p=p, gamma=gamma,
+                           q_halo=False)
+        if n:
+            local_timestep(self.patches, self.per_patch, dim=3, cfl=cfl)
+
+    def step(self, stream=None):
+        step_local(self.patches, self.neighbours, self.plan, self.a, self.b, gamma=self.gamma,
+                   cfl=self.cfl, max_eig=self.per_patch, schedule=self.schedule,
+                   workgroups=self.workgroups, stream=stream)
+        self.a, self.b = self.b, self.a
+
+    def state(self):
+        return self.a
+
+    def descriptors(self):
+        """Host copy of the descriptors in the caller's patch order."""
+        raw = self.patches.cpu().numpy()
+        return raw.view(PATCH_DTYPE)[self.inv].copy()
+
+    def max_eig(self):
+        """Host copy of the per-patch maxima of the latest state, caller's order."""
+        return self.per_patch[:self.n].cpu().numpy()[self.inv]
 
 
 class Stepper:

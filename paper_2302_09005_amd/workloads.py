@@ -355,3 +355,135 @@ def grid_uniform(d: int, counts, p: int, state, dx: float = None) -> Tuple[Patch
     for k in range(d + 2):
         q[k] = state[k]
     return grid, q
+
+
+# ---------------------------------------------------------------------------
+# Uneven batches: independent 3-D patches of mixed size and resolution level
+# ---------------------------------------------------------------------------
+UNEVEN_SIZES = (4, 8, 16)
+UNEVEN_RATIO = (4, 2, 1)
+UNEVEN_LEVELS = (2, 3, 4)
+
+
+@dataclass
+class UnevenBatch:
+    """A batch of 3-D patches of mixed size p_b and level l_b.
+
+    Patch b covers a cube of side 3^-l_b (factor-3 refinement, Section 2) with
+    p_b^3 volumes, so dx_b = 3^-l_b / p_b on every axis.  Every patch is
+    periodic onto itself (each face's neighbour is the patch itself), so the
+    patches are independent, as the patches of one batch handed to the
+    update are.  Blocks are compact [s][p^3], stored back to back in patch
+    order (``offsets``).
+    """
+    sizes: np.ndarray       # int[n]
+    levels: np.ndarray      # int[n]
+
+    def __post_init__(self):
+        self.sizes = np.asarray(self.sizes, dtype=np.int64)
+        self.levels = np.asarray(self.levels, dtype=np.int64)
+        if self.sizes.shape != self.levels.shape:
+            raise ValueError("sizes and levels differ in length")
+
+    @property
+    def n(self) -> int:
+        return int(self.sizes.shape[0])
+
+    @property
+    def d(self) -> int:
+        return 3
+
+    @property
+    def s(self) -> int:
+        return 5
+
+    @property
+    def dx(self) -> np.ndarray:
+        """float[n]: volume width of each patch."""
+        return 3.0 ** (-self.levels.astype(np.float64)) / self.sizes
+
+    def block_len(self) -> np.ndarray:
+        return self.s * self.sizes ** 3
+
+    def offsets(self) -> np.ndarray:
+        bl = self.block_len()
+        return np.concatenate([[0], np.cumsum(bl)[:-1]]).astype(np.int64) if self.n else \
+            np.zeros(0, np.int64)
+
+    def buffer_len(self) -> int:
+        return int(self.block_len().sum())
+
+    @property
+    def cells(self) -> int:
+        return int((self.sizes ** 3).sum())
+
+    def descriptors(self, dt=0.0) -> np.ndarray:
+        desc = np.zeros(self.n, dtype=PATCH_DTYPE)
+        off = self.offsets()
+        desc["q_in"] = off
+        desc["q_out"] = off
+        desc["p"] = self.sizes
+        desc["dx"] = self.dx[:, None]
+        desc["dt"] = dt
+        return desc
+
+    def neighbours(self) -> np.ndarray:
+        """int64[n, 6]: every face's neighbour is the patch itself."""
+        return np.repeat(np.arange(self.n, dtype=np.int64), 6).reshape(self.n, 6)
+
+    def block(self, flat: np.ndarray, b: int) -> np.ndarray:
+        """View of patch b's block in a flat buffer, shape [s, p, p, p]."""
+        p = int(self.sizes[b])
+        o = int(self.offsets()[b])
+        return flat[o:o + self.s * p ** 3].reshape(self.s, p, p, p)
+
+
+def uneven_batch(n: int = 20000, seed: int = 0, sizes=UNEVEN_SIZES, ratio=UNEVEN_RATIO,
+                 levels=UNEVEN_LEVELS, modes: int = 2) -> Tuple[UnevenBatch, np.ndarray]:
+    """Seeded uneven batch and its initial state (flat compact buffer).
+
+    With rng = numpy.random.default_rng(seed): sizes drawn per patch from
+    ``sizes`` with probabilities proportional to ``ratio`` (4^3 : 8^3 : 16^3
+    = 4 : 2 : 1 by default), then levels drawn uniformly from ``levels``, in
+    patch order.  Fields, per size class in ascending p and patch order: for
+    rho, p, u, v, w in that order, g = mean over ``modes`` modes of
+    sin(2 pi k . x + phi) in patch-local coordinates x = (i + 1/2) / p_b, with
+    k drawn from {-1, 0, 1}^3 minus zero (periodic on the patch) and phi from
+    U[0, 2 pi); then rho = 1 + 0.5 g, p = 1.25 + 0.75 g, u_j = 0.5 g, as for
+    the 4096 x 8^3 grid.
+    """
+    rng = np.random.default_rng(seed)
+    prob = np.asarray(ratio, dtype=np.float64)
+    prob = prob / prob.sum()
+    sz = rng.choice(np.asarray(sizes, dtype=np.int64), size=n, p=prob)
+    lv = rng.choice(np.asarray(levels, dtype=np.int64), size=n)
+    batch = UnevenBatch(sz, lv)
+    q = np.empty(batch.buffer_len())
+    off = batch.offsets()
+    for p in sorted(set(int(v) for v in sz)):
+        idx = np.nonzero(sz == p)[0]
+        m = idx.shape[0]
+        x = (np.arange(p) + 0.5) / p
+        zz, yy, xx = np.meshgrid(x, x, x, indexing="ij")
+        fields = []
+        for _ in range(5):
+            g = np.zeros((m, p, p, p))
+            for _ in range(modes):
+                k = rng.integers(-1, 2, size=(m, 3))
+                zero = ~k.any(axis=1)
+                while zero.any():
+                    k[zero] = rng.integers(-1, 2, size=(int(zero.sum()), 3))
+                    zero = ~k.any(axis=1)
+                phi = rng.uniform(0.0, 2 * np.pi, size=m)
+                arg = (2 * np.pi * (k[:, 0, None, None, None] * xx + k[:, 1, None, None, None] * yy
+                                    + k[:, 2, None, None, None] * zz) + phi[:, None, None, None])
+                g += np.sin(arg)
+            fields.append(g / modes)
+        rho = 1.0 + 0.5 * fields[0]
+        pres = 1.25 + 0.75 * fields[1]
+        qc = to_conserved(rho, [0.5 * g for g in fields[2:]], pres)  # [s, m, p, p, p]
+        qc = np.moveaxis(qc, 1, 0).reshape(m, -1)
+        blk = 5 * p ** 3
+        for j, b in enumerate(idx):
+            q[off[b]:off[b] + blk] = qc[j]
+    return batch, q

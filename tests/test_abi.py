@@ -148,3 +148,74 @@ def test_step_workspace_size_and_rejection_on_host():
     bad = list(args)
     bad[14] = 0x3000
     assert lib.fv_step_gather(*bad, None, 0x5000, 4096, None) == fv.FV_EINVAL
+
+
+def test_plan_mixed_sorts_by_size_and_fills_units():
+    batch, _ = W.uneven_batch(300, 2)
+    desc = batch.descriptors()
+    plan = fv.Plan(desc, device="cpu")
+    # stable sort, 16^3 first
+    for p, first, count in plan.classes():
+        idx = plan.order[first:first + count]
+        assert (batch.sizes[idx] == p).all() and (np.diff(idx) > 0).all()
+    assert sorted(plan.order.tolist()) == list(range(batch.n))
+    assert [c[0] for c in plan.classes()] == [16, 8, 4]
+    per_unit = {16: 1, 8: 4, 4: 16}
+    u = plan.units_host
+    assert plan.n_units == len(u) == sum(-(-c[2] // per_unit[c[0]]) for c in plan.classes())
+    covered = []
+    for rec in u:
+        assert 1 <= rec["count"] <= per_unit[rec["p"]]
+        idx = plan.order[rec["first"]:rec["first"] + rec["count"]]
+        assert (batch.sizes[idx] == rec["p"]).all()
+        covered += idx.tolist()
+    assert sorted(covered) == list(range(batch.n))
+    # biggest units first
+    assert (np.diff([{16: 0, 8: 1, 4: 2}[int(p)] for p in u["p"]]) >= 0).all()
+
+
+def test_plan_mixed_rejects_bad_batches():
+    batch, _ = W.uneven_batch(10, 1)
+    desc = batch.descriptors()
+    bad = desc.copy()
+    bad["p"][3] = 5
+    with pytest.raises(fv.FVError, match="patch 3"):
+        fv.Plan(bad, device="cpu")
+    with pytest.raises(fv.FVError):
+        fv.Plan(desc, device="cpu", dim=2)
+    empty = fv.Plan(desc[:0], device="cpu")
+    assert empty.n_units == 0 and empty.classes() == []
+
+
+def _plan_struct(classes, n_units):
+    c = fv.MixedPlan()
+    c.order, c.units, c.n_units = 0x7000, 0x8000, n_units
+    for k, (p, first, count) in enumerate(classes):
+        c.class_p[k], c.class_first[k], c.class_count[k] = p, first, count
+    return c
+
+
+def test_step_local_rejects_bad_arguments_on_host():
+    lib = fv.library()
+    good = _plan_struct([(16, 0, 2), (8, 2, 5), (4, 7, 17)], 2 + 2 + 2)
+
+    def call(plan=good, n=24, dim=3, s=5, gamma=1.4, cfl=0.4, schedule=1, wg=0, q_out=0x100000):
+        return lib.fv_step_local(0x1000, n, 0x2000, ctypes.byref(plan), 0x10000, 1000, q_out,
+                                 1000, dim, s, gamma, cfl, None, schedule, wg, None)
+    assert call(dim=2) == fv.FV_EUNSUPPORTED
+    assert call(s=4) == fv.FV_EINVAL
+    assert call(cfl=0.0) == fv.FV_EINVAL
+    assert call(gamma=1.0) == fv.FV_EINVAL
+    assert call(schedule=3) == fv.FV_EINVAL
+    assert call(wg=-1) == fv.FV_EINVAL
+    assert call(n=25) == fv.FV_EINVAL and "covers" in lib.fv_last_error().decode()
+    assert call(plan=_plan_struct([(16, 0, 2), (8, 2, 5), (4, 7, 17)], 7)) == fv.FV_EINVAL
+    assert "work units" in lib.fv_last_error().decode()
+    assert call(plan=_plan_struct([(16, 0, 2), (8, 3, 5), (4, 7, 17)], 6)) == fv.FV_EINVAL
+    assert call(plan=_plan_struct([(16, 0, 2), (5, 2, 5), (4, 7, 17)], 6)) == \
+        fv.FV_EUNSUPPORTED
+    assert call(q_out=0x10000 + 8) == fv.FV_EINVAL          # overlapping buffers
+    assert call(n=0) == fv.FV_OK                            # empty batch: no launch
+    assert lib.fv_local_timestep(0x1000, 4, None, 3, 0.4, None) == fv.FV_EINVAL
+    assert lib.fv_local_timestep(0x1000, 4, 0x2000, 3, -0.4, None) == fv.FV_EINVAL
+    assert lib.fv_local_timestep(0x1000, 0, None, 3, 0.4, None) == fv.FV_OK
