@@ -210,6 +210,77 @@ def fp32_path(grid, q, steps, warmup, ref_state):
             "speedup_vs_fp64_step": None}
 
 
+def uneven_path(seed, steps=50, dtype=None, tune=True, schedule=("persistent", 0)):
+    """The uneven AMR-like batch: 20 000 self-periodic 3-D patches of 4^3, 8^3
+    and 16^3 volumes (4:2:1), levels 2-4 (dx = 3^-l / p), local time steps.
+    The schedule is picked by the autotuner (per size class, persistent
+    grids, patch-wise); then ``steps`` steps are captured in one HIP graph
+    and the graph is replayed and timed, next to the same steps run eagerly.
+    """
+    import torch
+    from paper_2302_09005_amd import autotune, fv
+    from paper_2302_09005_amd import workloads as W
+    batch, q = W.uneven_batch(20000, seed)
+    st = fv.LocalStepper(batch.descriptors(), batch.neighbours(), q, dtype=dtype)
+    elem = 4 if dtype == np.float32 else 8
+    bytes_step = float(sum(algorithmic_bytes_per_cell(3, int(p), 5, elem) * int(p) ** 3
+                           for p in batch.sizes))
+    table = []
+    if tune:
+        best, table = autotune.tune(st, steps=3, warmup=1, patchwise=True)
+    else:
+        st.schedule, st.workgroups = schedule
+        best = schedule
+    # eager reference timing of the chosen schedule
+    for _ in range(2):
+        st.step()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        st.step()
+    t1.record()
+    torch.cuda.synchronize()
+    eager_ms = t0.elapsed_time(t1)
+    # graph capture of the whole multi-step loop (even count: buffers return)
+    n_cap = steps + (steps % 2)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(n_cap):
+                st.step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph.replay()  # warm
+    torch.cuda.synchronize()
+    reps = 3
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for r in range(reps):
+        graph.replay()
+        ev[r + 1].record()
+    torch.cuda.synchronize()
+    rep_ms = [ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]
+    graph_ms = float(np.median(rep_ms))
+    desc = st.descriptors()
+    finite = bool(torch.isfinite(st.state()).all().item())
+    ms_step = graph_ms / n_cap
+    return {"patches": batch.n, "volumes": batch.cells,
+            "class_counts": {str(p): int((batch.sizes == p).sum()) for p in (4, 8, 16)},
+            "dtype": "f32" if dtype == np.float32 else "f64",
+            "schedule": {"chosen": list(best),
+                         "tuned_us_per_step": [[s_, w_, round(u_, 2)] for s_, w_, u_ in table]},
+            "graph_steps": n_cap, "graph_ms_per_step": ms_step,
+            "eager_ms_per_step": eager_ms / steps,
+            "cell_updates_per_s": batch.cells / (ms_step * 1e-3),
+            "algorithmic_bytes_per_step": bytes_step,
+            "achieved_gbs": bytes_step / (ms_step * 1e-3) / 1e9,
+            "hbm_frac": bytes_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "t_range": [float(desc["t"].min()), float(desc["t"].max())],
+            "state_finite": finite}
+
+
 def copy_calibration(mib=1024, reps=5):
     """Plain device copy of a known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -230,6 +301,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven-batch detail (20 000 mixed-size patches)")
+    ap.add_argument("--uneven-schedule", default=None, metavar="SCHED:WG",
+                    help="fix the uneven-batch schedule (e.g. persistent:0) instead of tuning")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of CPU-oracle work for the baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -293,6 +368,19 @@ def main():
     f32 = fp32_path(grid, q, args.steps, args.warmup, state)
     f32["speedup_vs_fp64_step"] = (total_ms / args.steps) / f32["ms_per_step"]
 
+    # uneven AMR-like batch with local time steps (FP64, then FP32 bulk)
+    fixed = None
+    if args.uneven_schedule:
+        sched, wg = args.uneven_schedule.split(":")
+        fixed = (sched, int(wg))
+    uneven = None if args.no_uneven else (
+        uneven_path(args.seed) if fixed is None else
+        uneven_path(args.seed, tune=False, schedule=fixed))
+    uneven32 = None
+    if uneven is not None:
+        uneven32 = uneven_path(args.seed, dtype=np.float32, tune=False,
+                               schedule=tuple(uneven["schedule"]["chosen"]))
+
     cells = grid.cells
     value = cells * args.steps / (total_ms * 1e-3)
     bpc = algorithmic_bytes_per_cell(d, p, s, 8)
@@ -325,7 +413,9 @@ def main():
                    "update_us_median": float(np.median(upd_ms) * 1e3),
                    "final_lambda": lam_final, "state_finite": finite,
                    "plain_halo_path": plain,
-                   "fp32_path": f32},
+                   "fp32_path": f32,
+                   "uneven_batch": uneven,
+                   "uneven_batch_fp32": uneven32},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid, grid.pack(q), args.cpu_budget, 100)
