@@ -281,6 +281,112 @@ def uneven_path(seed, steps=50, dtype=None, tune=True, schedule=("persistent", 0
             "state_finite": finite}
 
 
+def sweep_2d_p17(seed, ns, reps):
+    """The paper's Fig. 1 shape (Section 5): 2-D Euler, patches of 17^2 with a
+    halo of one, N patches per update call, timed three ways: device-resident
+    (one batched launch), including the host-to-device copy of the N input
+    blocks and the device-to-host copy of the N output blocks (pinned host
+    memory; the paper's timings include all transfers), and patch-wise (one
+    launch per patch, the paper's other loop order), eagerly and captured in
+    one HIP graph.  Prints one JSON line per N."""
+    import torch
+    from paper_2302_09005_amd import fv
+    from paper_2302_09005_amd import workloads as W
+    per_axis = int(np.ceil(np.sqrt(max(ns))))
+    grid, q = W.grid_2d_smooth(per_axis, 17, seed=seed)
+    flat = grid.pack(q)
+    blk_in, blk_out = grid.block_halo, grid.block_compact
+    q_host = torch.from_numpy(flat).pin_memory()
+    out_host = torch.empty(grid.n * blk_out, dtype=torch.float64).pin_memory()
+    q_dev = q_host.to("cuda")
+    out_dev = torch.zeros(grid.n * blk_out, dtype=torch.float64, device="cuda")
+    # one CFL step of the whole grid, on the device
+    per = torch.empty(grid.n, dtype=torch.float64, device="cuda")
+    dt_dev = torch.empty(1, dtype=torch.float64, device="cuda")
+    desc_all = grid.descriptors(out_halo=False)
+    pd_all = fv.upload_patches(desc_all)
+    fv.max_eigenvalue(pd_all, q_dev, per, dim=2, p=17)
+    fv.cfl_timestep(pd_all, per, dim=2, dt_out=dt_dev)
+    desc_all["dt"] = dt_dev.item()
+    pd_all = fv.upload_patches(desc_all)
+    rec = W.PATCH_DTYPE.itemsize
+    me = torch.empty(grid.n, dtype=torch.float64, device="cuda")
+    cells_per_patch = 17 * 17
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def batched(n):
+        fv.batch_update(pd_all[:n * rec], q_dev, out_dev, dim=2, p=17, q_out_halo=False,
+                        max_eig=me)
+
+    def patchwise(n):
+        for i in range(n):
+            fv.batch_update(pd_all[i * rec:(i + 1) * rec], q_dev, out_dev, dim=2, p=17,
+                            q_out_halo=False, max_eig=me)
+
+    for n in ns:
+        row = {"sweep": "2d-euler-p17", "N": n, "volumes": n * cells_per_patch}
+        # batched, device-resident: kernel time from dispatch-recorded events
+        batched(n)
+        hip = HipEvents(reps)
+        a, b = ev(), ev()
+        torch.cuda.synchronize()
+        a.record()
+        for i in range(reps):
+            fv.set_launch_events(hip.start[i], hip.stop[i])
+            batched(n)
+        fv.set_launch_events(None, None)
+        b.record()
+        torch.cuda.synchronize()
+        row["batched_kernel_us"] = float(np.median(hip.elapsed_ms()) * 1e3)
+        hip.destroy()
+        row["batched_call_us"] = a.elapsed_time(b) * 1e3 / reps
+        # batched including host<->device transfers of the N blocks
+        ts = []
+        for _ in range(reps):
+            a, b = ev(), ev()
+            a.record()
+            q_dev[:n * blk_in].copy_(q_host[:n * blk_in], non_blocking=True)
+            batched(n)
+            out_host[:n * blk_out].copy_(out_dev[:n * blk_out], non_blocking=True)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) * 1e3)
+        row["batched_with_transfers_us"] = float(np.median(ts))
+        # patch-wise: eager launches, and the same launches captured in one graph
+        pw_reps = max(1, min(reps, 4096 // n))
+        a, b = ev(), ev()
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(pw_reps):
+            patchwise(n)
+        b.record()
+        torch.cuda.synchronize()
+        row["patchwise_eager_us"] = a.elapsed_time(b) * 1e3 / pw_reps
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                patchwise(n)
+        torch.cuda.current_stream().wait_stream(side)
+        graph.replay()
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(pw_reps):
+            graph.replay()
+        b.record()
+        torch.cuda.synchronize()
+        row["patchwise_graph_us"] = a.elapsed_time(b) * 1e3 / pw_reps
+        del graph
+        for k in ("batched_kernel_us", "batched_call_us", "batched_with_transfers_us",
+                  "patchwise_eager_us", "patchwise_graph_us"):
+            row[k.replace("_us", "_cell_updates_per_s")] = n * cells_per_patch / (row[k] * 1e-6)
+        print(json.dumps(row), flush=True)
+
+
 def copy_calibration(mib=1024, reps=5):
     """Plain device copy of a known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -303,6 +409,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch detail (20 000 mixed-size patches)")
+    ap.add_argument("--sweep-2d-p17", action="store_true",
+                    help="only run the 2-D p=17 sweep over N patches per call (one JSON line per N)")
     ap.add_argument("--uneven-schedule", default=None, metavar="SCHED:WG",
                     help="fix the uneven-batch schedule (e.g. persistent:0) instead of tuning")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
@@ -323,6 +431,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.sweep_2d_p17:
+        sweep_2d_p17(args.seed, [1, 4, 16, 64, 256, 1024, 4096, 16384], 20)
         return
 
     from paper_2302_09005_amd import fv
