@@ -11,10 +11,14 @@ step of the next step.  Inputs are resident in HBM before the timed region
 starts.  The paper's interface (halo'd blocks, update, separate halo fill) is
 timed afterwards and reported under detail.plain_halo_path.
 
+The timed steps run as one HIP graph (captured once, replayed once untimed and
+once timed with events on the stream that runs it), so consecutive steps are
+not separated by host launch gaps.
+
 Prints ONE JSON line: cell-updates/s over the timed steps, the roofline of the
-dominant kernel (the update; algorithmic bytes / its average duration measured
-with HIP events on the stream it runs on) and the CPU oracle timed on a
-bounded sample of the same workload.
+dominant kernel (the update; algorithmic bytes / its average duration, the
+timed replay divided by the steps) and the CPU oracle timed on a bounded sample
+of the same workload.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu-baseline]
 """
@@ -170,30 +174,40 @@ def plain_path(grid, q, steps):
 
 
 def fp32_path(grid, q, steps, warmup, ref_state):
-    """The same fused step with FP32 state (FP64 maxima / CFL): throughput, kernel
-    time, roofline at the FP32 algorithmic bytes, and the relative difference
-    to the FP64 state after the same number of steps."""
+    """The same fused step with FP32 state (FP64 maxima / CFL), run exactly as
+    the FP64 line (eager warm-up, a graph of the timed steps replayed twice,
+    20 eager steps): throughput, kernel time, roofline at the FP32
+    algorithmic bytes, and the relative difference to the FP64 state after
+    the same steps."""
     import torch
     from paper_2302_09005_amd import fv
     st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
                     grid.pack_compact(q), dim=grid.d, p=grid.p, mode="fused", dtype=np.float32)
     for _ in range(warmup):
         st.step()
-    hip = HipEvents(steps)
     stream = torch.cuda.current_stream()
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(steps):
+                st.update()
+                st.swap()
+    stream.wait_stream(side)
+    graph.replay()
     torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record(stream)
-    for i in range(steps):
-        fv.set_launch_events(hip.start[i], hip.stop[i])
-        st.update()
-        st.swap()
-    fv.set_launch_events(None, None)
+    graph.replay()
     t1.record(stream)
     torch.cuda.synchronize()
-    upd = hip.elapsed_ms()
-    hip.destroy()
     total = t0.elapsed_time(t1)
+    del graph
+    for _ in range(20):
+        st.update()
+        st.swap()
+    torch.cuda.synchronize()
     a = st.state().double()
     r = ref_state
     s = grid.s
@@ -202,10 +216,11 @@ def fp32_path(grid, q, steps, warmup, ref_state):
     l2 = float((d.norm(dim=1) / rv.norm(dim=1)).max())
     li = float((d.abs().amax(dim=1) / rv.abs().amax(dim=1)).max())
     bpc = algorithmic_bytes_per_cell(grid.d, grid.p, grid.s, 4)
+    upd_us = total * 1e3 / steps
     return {"steps": steps, "cell_updates_per_s": grid.cells * steps / (total * 1e-3),
-            "ms_per_step": total / steps, "update_us": float(upd.mean() * 1e3),
+            "ms_per_step": total / steps, "update_us": upd_us,
             "algorithmic_bytes_per_cell": bpc,
-            "update_hbm_frac": bpc * grid.cells / (upd.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "update_hbm_frac": bpc * grid.cells / (upd_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
             "rel_l2_vs_fp64": l2, "rel_linf_vs_fp64": li,
             "speedup_vs_fp64_step": None}
 
@@ -449,25 +464,48 @@ def main():
         st.step()
     torch.cuda.synchronize()
 
-    # Per-launch kernel time: HIP events recorded by the update's own dispatch
-    # packet (fv_set_launch_events), i.e. the kernel's execution on the stream
-    # it runs on; the whole timed region is bracketed by torch events.
-    hip = HipEvents(args.steps)
+    # The timed region: the K steps captured once as a HIP graph (one fused
+    # kernel node per step, so the steps run back to back without host
+    # launch gaps), replayed once untimed and once timed with events on the
+    # stream that runs it.  The per-launch kernel time is the timed replay
+    # divided by K (an upper bound: it includes the gap between graph nodes).
     stream = torch.cuda.current_stream()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(args.steps):
+                st.update()
+                st.swap()
+    stream.wait_stream(side)
+    graph.replay()
+    torch.cuda.synchronize()
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_start.record(stream)
-    for i in range(args.steps):
+    graph.replay()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    upd_ms = np.full(args.steps, total_ms / args.steps)
+    del graph
+
+    # for comparison: eager launches timed by HIP events that the dispatch
+    # packet itself records (fv_set_launch_events), and the eager step time
+    n_eager = 20
+    hip = HipEvents(n_eager)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(n_eager):
         fv.set_launch_events(hip.start[i], hip.stop[i])
         st.update()
         st.swap()
     fv.set_launch_events(None, None)
-    t_end.record(stream)
+    e1.record(stream)
     torch.cuda.synchronize()
-
-    total_ms = t_start.elapsed_time(t_end)
-    upd_ms = hip.elapsed_ms()
+    eager_dispatch_us = float(np.median(hip.elapsed_ms()) * 1e3)
+    eager_step_us = e0.elapsed_time(e1) * 1e3 / n_eager
     hip.destroy()
     state = st.state()
     finite = bool(torch.isfinite(state).all().item())
@@ -521,7 +559,9 @@ def main():
                      "algorithmic_bytes_per_cell": bpc,
                      "kernel_avg_us": upd_ms.mean() * 1e3},
         "detail": {"update_cell_updates_per_s": cells / upd_s,
-                   "update_us_median": float(np.median(upd_ms) * 1e3),
+                   "timing": "HIP graph of the timed steps; kernel_avg_us = replay time / steps",
+                   "eager_dispatch_event_us": eager_dispatch_us,
+                   "eager_step_us": eager_step_us,
                    "final_lambda": lam_final, "state_finite": finite,
                    "plain_halo_path": plain,
                    "fp32_path": f32,

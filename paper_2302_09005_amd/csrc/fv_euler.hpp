@@ -49,6 +49,28 @@ __device__ __forceinline__ double recip(double x) {
 }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Square root from the hardware reciprocal-square-root estimate y ~ 1/sqrt(x)
+// by Goldschmidt's iteration on g ~ sqrt(x), h ~ 1/(2 sqrt(x)) followed by
+// two Newton corrections g += (x - g^2) h.  Without the range scaling of the
+// library routine: exact to the last bit or two for normal arguments, which
+// is all a sound speed needs.  Zeros and +inf map to themselves, negative
+// arguments and NaN to NaN.
+__device__ __forceinline__ double sqrt_fast(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = 0.5 * y;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  g = fma(d, h, g);
+  // -0, +0 and +inf (class bits 5, 6 and 9): the iteration would give NaN
+  return __builtin_amdgcn_class(x, 0x260) ? x : g;
+}
+__device__ __forceinline__ float sqrt_fast(float x) { return sqrtf(x); }
+
 // What a face needs from one adjacent volume besides its conserved state:
 // 1/rho, pressure and sound speed.  Computing 1/rho once per volume replaces
 // the d + 2 divisions of the textbook formulas.
@@ -65,7 +87,7 @@ __device__ __forceinline__ Prim<T> decode(const T (&q)[D + 2], T gamma) {
 #pragma unroll
   for (int k = 1; k < D; ++k) jj = fma(q[1 + k], q[1 + k], jj);
   w.p = (gamma - T(1)) * fma(T(-0.5) * jj, w.ir, q[D + 1]);
-  w.c = sqrt(gamma * w.p * w.ir);
+  w.c = sqrt_fast(gamma * w.p * w.ir);
   return w;
 }
 
@@ -81,6 +103,10 @@ __device__ __forceinline__ T max_wave_speed(const T (&q)[D + 2], const Prim<T>& 
 // Rusanov flux across a face normal to axis K between left state L and right
 // state R (Section 2, eq. (4)):
 //   F = 1/2 [ f^K(L) + f^K(R) - a (R - L) ],  a = max(|u_K(L)| + c_L, |u_K(R)| + c_R).
+// Twice the Rusanov flux across a face with normal along axis K, 2F =
+// f(L) + f(R) - a (R - L) (eq. (4)); the caller folds the factor 1/2 into
+// dt/dx, which is exact in binary floating point and so changes no bit of
+// the update.
 template <typename T, int D, int K>
 __device__ __forceinline__ void rusanov(const T (&qL)[D + 2], const Prim<T>& wL,
                                         const T (&qR)[D + 2], const Prim<T>& wR,
@@ -100,7 +126,7 @@ __device__ __forceinline__ void rusanov(const T (&qL)[D + 2], const Prim<T>& wL,
   fL[D + 1] = (qL[D + 1] + wL.p) * uL;
   fR[D + 1] = (qR[D + 1] + wR.p) * uR;
 #pragma unroll
-  for (int m = 0; m < S; ++m) F[m] = T(0.5) * fma(-a, qR[m] - qL[m], fL[m] + fR[m]);
+  for (int m = 0; m < S; ++m) F[m] = fma(-a, qR[m] - qL[m], fL[m] + fR[m]);
 }
 
 }  // namespace fvk

@@ -7,19 +7,35 @@
 
 #include "../../include/fv.h"
 
+#ifndef FV_LDS_CPAD
+#define FV_LDS_CPAD 0
+#endif
+#ifndef FV_LDS_FPAD
+#define FV_LDS_FPAD 0
+#endif
+#ifndef FV_ZSPLIT_3D8
+#define FV_ZSPLIT_3D8 1
+#endif
+
 namespace fvk {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Chunks along the marching axis per patch in the single-size update
+// kernels (each chunk marches P / ZS planes in a wave of its own).
+template <int D, int P>
+constexpr int zsplit() { return D == 3 && P == 8 ? FV_ZSPLIT_3D8 : 1; }
 
 // Geometry of a D-dimensional patch of P^D volumes with a halo of one volume,
 // and of the plane-marching update that processes it.
 //
 // The update walks the last axis (z in 3-D, y in 2-D): one lane owns one
-// column of volumes along that axis, so a patch occupies P^(D-1) lanes
-// ("LANES") and PPW patches share one workgroup of NTW threads when
-// LANES < NTW (NTW = 64 for the single-size kernels, 256 in the mixed-size
-// persistent kernel).
-template <int D, int P, int NTW = 64>
+// column of volumes along that axis, so a patch chunk occupies P^(D-1) lanes
+// ("LANES").  A patch is marched in ZS chunks of P / ZS planes each, side by
+// side, so it takes TPP = ZS * LANES threads, and PPW patches share one
+// workgroup of NTW threads when TPP < NTW (NTW = 64 for the single-size
+// kernels, 256 in the mixed-size persistent kernel).
+template <int D, int P, int NTW = 64, int ZS = zsplit<D, P>()>
 struct Geo {
   static constexpr int S = D + 2;                    // unknowns
   static constexpr int W = P + 2;                    // volumes per axis incl. halo
@@ -27,18 +43,26 @@ struct Geo {
   static constexpr int VOUT = ipow(P, D);            // volumes of a compact block
   static constexpr int SM = ipow(W, D - 1);          // halo'd stride of the marching axis
   static constexpr int SMO = ipow(P, D - 1);         // compact stride of the marching axis
-  static constexpr int LANES = ipow(P, D - 1);       // lanes per patch (one column each)
-  static constexpr int PPW = LANES >= NTW ? 1 : NTW / LANES;  // patches per workgroup
-  static constexpr int NT = ((PPW * LANES + 63) / 64) * 64; // workgroup size
+  static constexpr int LANES = ipow(P, D - 1);       // lanes per chunk (one column each)
+  static constexpr int CHUNKS = ZS;                  // chunks per patch
+  static constexpr int PC = P / ZS;                  // planes per chunk
+  static constexpr int TPP = ZS * LANES;             // threads per patch
+  static constexpr int PPW = TPP >= NTW ? 1 : NTW / TPP;  // patches per workgroup
+  static constexpr int NT = ((PPW * TPP + 63) / 64) * 64; // workgroup size
   static constexpr int RING = D == 3 ? 4 * P : 2;    // face-halo volumes around one plane
   static constexpr int NEXTRA = D == 3 ? 2 * P : 1;  // in-plane faces on the high boundary
   static constexpr int NCELL = LANES + RING;         // volumes of one plane incl. its ring
   static constexpr int NV = S + 3;                   // values kept per volume: q, 1/rho, p, c
   static constexpr int NF = LANES + (D == 3 ? P : 1);  // in-plane faces per axis and plane
-  static constexpr int CELLBUF = NV * NCELL;
-  static constexpr int FACEBUF = (D - 1) * S * NF;
+  // LDS strides of one value across a plane's volumes and faces (padded so
+  // that the two halves of a paired 64-bit access fall in different banks)
+  static constexpr int CST = NCELL + FV_LDS_CPAD;
+  static constexpr int FST = NF + FV_LDS_FPAD;
+  static constexpr int CELLBUF = NV * CST;
+  static constexpr int FACEBUF = (D - 1) * S * FST;
   static constexpr int SLOT = CELLBUF > FACEBUF ? CELLBUF : FACEBUF;  // LDS elements per patch
   static_assert(RING <= LANES, "every ring volume needs its own lane");
+  static_assert(P % ZS == 0 && (ZS == 1 || LANES == 64), "chunks are whole planes of one wave");
   static_assert(NEXTRA <= LANES, "every high-boundary face needs its own lane");
 };
 

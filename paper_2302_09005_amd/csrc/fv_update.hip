@@ -49,40 +49,58 @@ namespace {
 // positive and decreases as h grows, so an integer max of it is a min of h.
 constexpr unsigned long long kInfBits = 0x7ff0000000000000ull;
 
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double uni(double v) {
+  return __longlong_as_double(uni((int64_t)__double_as_longlong(v)));
+}
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // Per-workgroup outputs of the update body for the caller's epilogue.
 struct BodyOut {
   double lam;    // maximum of the new state of this thread's patch (NaN if skipped)
   double hmin;   // smallest volume width of that patch
   bool in_range; // this thread's slot holds a patch
+  bool lead;     // this thread carries its patch's results (lam valid here)
   int slot;      // slot of this thread in the workgroup
-  int l;         // lane within the slot
 };
 
-// The update of the (up to PPW) patches of one workgroup of NTW threads.
-// b: the patch of this thread's slot (-1: none).  lds: PPW * SLOT elements,
-// red: NT / 64 elements, both shared.  MODE: see StepMode (kLocalDt needs a
-// writable descriptor array and cfl).
-template <typename T, int D, int P, int NTW, bool GATHER, int MODE>
+// The update of the (up to PPW) patches of one workgroup of NTW threads, each
+// marched in ZS chunks.  b: the patch of this thread's slot (-1: none).
+// lds: PPW * ZS * SLOT elements, red: NT / 64 elements, both shared.  MODE:
+// see StepMode (kLocalDt needs a writable descriptor array and cfl).
+template <typename T, int D, int P, int NTW, int ZS, bool GATHER, int MODE>
 __device__ __forceinline__ BodyOut update_body(
     const fv_patch* __restrict__ patches, int64_t n, const int64_t* __restrict__ neighbours,
     const T* __restrict__ qin, int64_t qin_len, T* __restrict__ qout, int64_t qout_len,
     int out_halo, T gamma, const double* __restrict__ dt_dev, double* __restrict__ max_eig,
     double cfl, int64_t b, T* __restrict__ lds, T* __restrict__ red) {
-  using G = Geo<D, P, NTW>;
+  using G = Geo<D, P, NTW, ZS>;
   constexpr int S = G::S;
+  constexpr int PC = G::PC;  // planes of this thread's chunk
   constexpr int K = D - 1;  // marching axis
   constexpr int W = G::W;
   constexpr int LANES = G::LANES;
-  constexpr int NCELL = G::NCELL;
-  constexpr int NF = G::NF;
+  constexpr int NCELL = G::CST;  // stride of one value in the plane buffer
+  constexpr int NF = G::FST;     // stride of one value in the face buffer
   // strides of the input blocks: component, marching-axis plane
   constexpr int CS = GATHER ? G::VOUT : G::VIN;
   constexpr int PS = GATHER ? G::SMO : G::SM;
 
   const int tid = threadIdx.x;
-  const int slot = G::PPW == 1 ? 0 : tid / LANES;
-  const int l = G::PPW == 1 ? tid : tid - slot * LANES;
+  const int slot = G::PPW == 1 ? 0 : tid / G::TPP;
+  const int tp = G::PPW == 1 ? tid : tid - slot * G::TPP;  // thread within the patch
+  const int chunk = ZS == 1 ? 0 : tp / LANES;
+  const int l = ZS == 1 ? tp : tp - chunk * LANES;
+  const int p0 = chunk * PC;  // first plane of the chunk
   const bool in_range = (G::PPW == 1 || slot < G::PPW) && b >= 0 && b < n;
+  const bool lead = in_range && l == 0 && chunk == 0;  // writes the patch results
   const int x = l % P;
   const int y = (D == 3) ? l / P : 0;
   const bool has_ring = l < G::RING;
@@ -110,7 +128,7 @@ __device__ __forceinline__ BodyOut update_body(
     dt_used = dt;
     t_used = pd.t;
 #pragma unroll
-    for (int j = 0; j < D; ++j) r[j] = T(dt / pd.dx[j]);
+    for (int j = 0; j < D; ++j) r[j] = T(dt / pd.dx[j]) * T(0.5);  // rusanov gives 2F
     hmin = pd.dx[0];
 #pragma unroll
     for (int j = 1; j < D; ++j) hmin = fmin(hmin, pd.dx[j]);
@@ -147,10 +165,26 @@ __device__ __forceinline__ BodyOut update_body(
           idx = q4 == 0 ? (hasnb ? P - 1 : 0) : (hasnb ? 0 : P - 1);
         }
         ring_src = (hasnb ? nbo[q4] : off_in) + idx;
+      } else {
+        ring_src = off_in + x + (D == 3 ? y * P : 0);  // own column, never used
       }
     }
   }
-  T* cell = lds + (ok ? slot * G::SLOT : 0);  // plane buffer [NV][NCELL]
+  if constexpr (G::PPW == 1) {
+    // one patch per workgroup: every lane read the same descriptor, so its
+    // values live in scalar registers
+    ok = __builtin_amdgcn_readfirstlane((int)ok) != 0;
+    off_in = uni(off_in);
+    off_out = uni(off_out);
+    lo_base = uni(lo_base);
+    hi_base = uni(hi_base);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r[j] = uni(r[j]);
+    hmin = uni(hmin);
+    dt_used = uni(dt_used);
+    t_used = uni(t_used);
+  }
+  T* cell = lds + (ok ? (slot * ZS + chunk) * G::SLOT : 0);  // plane buffer [NV][NCELL]
   T* face = cell;                             // face buffers, same storage
 
   // in-plane element index of the own column (compact and halo'd) and of
@@ -171,27 +205,25 @@ __device__ __forceinline__ BodyOut update_body(
   const int64_t ostride = out_halo ? G::SM : G::SMO;
   const int64_t ocomp = out_halo ? G::VIN : G::VOUT;
 
-  const T* gin = qin + off_in + col_in;
-  const T* glo = qin + lo_base + col_c;
-  const T* ghi = qin + hi_base + col_c;
-  const T* gring = GATHER ? qin + ring_src : qin + off_in + ring_h;
-  T* gout = qout + off_out + col_out;
+  // the chunk's own planes p0 .. p0+PC-1 (storage plane j = 1 + plane in a
+  // halo'd block, = plane in a compact one), the plane below and the plane
+  // above it (halo planes, or planes of the neighbouring chunks)
+  const int64_t jin = GATHER ? p0 : p0 + 1;
+  const T* gin = qin + off_in + col_in + jin * PS;
+  const T* glo = (GATHER && chunk == 0) ? qin + lo_base + col_c : gin - PS;
+  const T* ghi = (GATHER && chunk == ZS - 1) ? qin + hi_base + col_c : gin + (int64_t)PC * PS;
+  const T* gring = (GATHER ? qin + ring_src : qin + off_in + ring_h + PS) + (int64_t)p0 * PS;
+  T* gout = qout + off_out + col_out + (int64_t)p0 * ostride;
 
-  // unknown m of the own column at marching-axis storage plane j in [0, P+1]
-  // (0 and P+1 are the halo planes)
+  // unknown m of the own column at chunk storage plane j in [0, PC+1] (0 and
+  // PC+1: the planes below and above the chunk)
   auto ld_own = [&](int j, int m) -> T {
-    if constexpr (GATHER) {
-      if (j == 0) return glo[(int64_t)m * CS];
-      if (j == P + 1) return ghi[(int64_t)m * CS];
-      return gin[(int64_t)m * CS + (int64_t)(j - 1) * PS];
-    } else {
-      return gin[(int64_t)m * CS + (int64_t)j * PS];
-    }
+    if (j == 0) return glo[(int64_t)m * CS];
+    if (j == PC + 1) return ghi[(int64_t)m * CS];
+    return gin[(int64_t)m * CS + (int64_t)(j - 1) * PS];
   };
-  // unknown m of the ring volume at interior plane j in [1, P]
-  auto ld_ring = [&](int j, int m) -> T {
-    return gring[(int64_t)m * CS + (int64_t)(GATHER ? j - 1 : j) * PS];
-  };
+  // unknown m of the ring volume at chunk plane j in [1, PC]
+  auto ld_ring = [&](int j, int m) -> T { return gring[(int64_t)m * CS + (int64_t)(j - 1) * PS]; };
   auto st_out = [&](int pl, int m, T v) { gout[(int64_t)m * ocomp + (int64_t)pl * ostride] = v; };
 
   // ---- prologue: planes -1 and 0, first marching-axis face ---------------
@@ -210,8 +242,7 @@ __device__ __forceinline__ BodyOut update_body(
     for (int m = 0; m < S; ++m) {
       qlo[m] = ld_own(0, m);
       qc[m] = ld_own(1, m);
-      qnx[m] = ld_own(2, m);
-      if (has_ring) rraw[m] = ld_ring(1, m);
+      rraw[m] = ld_ring(1, m);  // lanes without a ring volume read their own column
     }
   }
   Prim<T> wc = decode<T, D>(qc, gamma);
@@ -234,24 +265,24 @@ __device__ __forceinline__ BodyOut update_body(
 
   // fully unrolled for small patches so that the rolling registers are
   // renamed instead of copied
-  constexpr int UNROLL = P <= 8 ? P : 2;
+  constexpr int UNROLL = PC <= 8 ? PC : 2;
 #pragma unroll UNROLL
-  for (int pl = 0; pl < P; ++pl) {
-    T rnext[S], qnn[S];
+  for (int pl = 0; pl < PC; ++pl) {
+    // loads for the next plane: its own volumes (needed for the
+    // marching-axis face in D) and its ring (needed in the next A)
+    T rnext[S];
 #pragma unroll
     for (int m = 0; m < S; ++m) {
       rnext[m] = rraw[m];
-      qnn[m] = qnx[m];
+      qnx[m] = qc[m];
     }
     if (act) {
-      if (has_ring && pl + 1 < P) {
+      if (pl + 1 < PC) {
 #pragma unroll
         for (int m = 0; m < S; ++m) rnext[m] = ld_ring(pl + 2, m);
       }
-      if (pl + 3 <= P + 1) {
 #pragma unroll
-        for (int m = 0; m < S; ++m) qnn[m] = ld_own(pl + 3, m);
-      }
+      for (int m = 0; m < S; ++m) qnx[m] = ld_own(pl + 2, m);
     }
     // A. publish own and ring volumes of this plane
     if (act) {
@@ -293,7 +324,10 @@ __device__ __forceinline__ BodyOut update_body(
         rusanov<T, D, 1>(qn, wn, qc, wc, Fl1);
       }
       if (l < G::NEXTRA) {
-        // high-boundary face: interior volume at coordinate P-1 against the ring
+        // high-boundary face: interior volume at coordinate P-1 against the
+        // ring.  A y face reads its two in-plane momenta swapped, so that one
+        // x-direction flux serves both directions (the same operations on the
+        // same values: bit-identical to a y-direction flux).
         const bool ydir = (D == 3) && l >= P;
         const int t = ydir ? l - P : l;
         const int lc = D == 3 ? (ydir ? (P - 1) * P + t : t * P + (P - 1)) : P - 1;
@@ -367,10 +401,7 @@ __device__ __forceinline__ BodyOut update_body(
       wc = wu;
     }
 #pragma unroll
-    for (int m = 0; m < S; ++m) {
-      qnx[m] = qnn[m];
-      rraw[m] = rnext[m];
-    }
+    for (int m = 0; m < S; ++m) rraw[m] = rnext[m];
     __syncthreads();
   }
 
@@ -387,6 +418,14 @@ __device__ __forceinline__ BodyOut update_body(
 #pragma unroll
         for (int w = 1; w < LANES / 64; ++w) lam = nanmax_pos(lam, red[w]);
       }
+    } else if constexpr (ZS > 1) {
+      // one wave per chunk: fold the chunks of each patch
+      if (l == 0) red[tid >> 6] = lam;
+      __syncthreads();
+      if (lead) {
+#pragma unroll
+        for (int c = 1; c < ZS; ++c) lam = nanmax_pos(lam, red[(tid >> 6) + c]);
+      }
     }
   } else {
     // odd cross-sections (e.g. 17 lanes): gather through LDS
@@ -397,18 +436,30 @@ __device__ __forceinline__ BodyOut update_body(
     }
   }
   const double lam_b = ok ? double(lam) : __builtin_nan("");
-  if (in_range && l == 0 && max_eig) max_eig[b] = lam_b;
+  if (lead && max_eig) max_eig[b] = lam_b;
   if constexpr (MODE == kLocalDt) {
     // local time stepping: this patch moves to t + dt and takes its own
     // next CFL step from the new state
-    if (in_range && l == 0 && ok) {
+    if (lead && ok) {
       fv_patch* pw = const_cast<fv_patch*>(patches) + b;
       pw->t = t_used + dt_used;
       pw->dt = cfl * hmin / ((double)D * lam_b);
     }
   }
-  return BodyOut{lam_b, hmin, in_range, slot, l};
+  return BodyOut{lam_b, hmin, in_range, lead, slot};
 
+}
+
+// Workgroup w of a launch runs on XCD w mod 8 (round-robin dispatch over the
+// eight XCDs, each with its own L2).  Hand each XCD a contiguous range of
+// launch items instead, so that neighbouring patches, whose face layers a
+// patch reads, are updated on the same XCD at about the same time and meet
+// in its L2.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t w, int64_t nwg) {
+  constexpr int64_t kXcd = 8;
+  const int64_t q = nwg / kXcd, r = nwg % kXcd;
+  const int64_t x = w % kXcd, k = w / kXcd;
+  return x * q + (x < r ? x : r) + k;
 }
 
 template <typename T, int D, int P, bool GATHER, int MODE>
@@ -421,22 +472,23 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
                  CflOut cflo, const int64_t* __restrict__ order, int64_t order_base,
                  int64_t count) {
   using G = Geo<D, P>;
-  __shared__ T lds[G::PPW * G::SLOT];
+  __shared__ T lds[G::PPW * G::CHUNKS * G::SLOT];
   __shared__ T red[G::NT / 64];
   const int tid = threadIdx.x;
-  const int slot = G::PPW == 1 ? 0 : tid / G::LANES;
+  const int slot = G::PPW == 1 ? 0 : tid / G::TPP;
   // the patch of this thread's slot: launch item i is patch i, or the
   // patch order[order_base + i] when the launch covers a sorted range
-  const int64_t i = (int64_t)blockIdx.x * G::PPW + slot;
+  const int64_t wgi = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int64_t i = wgi * G::PPW + slot;
   int64_t b = -1;
   if (slot < G::PPW && i < count) b = order ? order[order_base + i] : i;
-  const BodyOut bo = update_body<T, D, P, 64, GATHER, MODE == kLocalDt ? kLocalDt : kPlain>(
+  const BodyOut bo =
+      update_body<T, D, P, 64, G::CHUNKS, GATHER, MODE == kLocalDt ? kLocalDt : kPlain>(
       patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo, gamma, dt_dev, max_eig,
       cflo.cfl, b, lds, red);
   const double lam_b = bo.lam;
   const double hmin = bo.hmin;
-  const bool in_range = bo.in_range;
-  const int l = bo.l;
+  const bool lead = bo.lead;
   if constexpr (MODE == kGlobalCfl) {
     // Fused CFL step.  Patch maxima and smallest volume widths are folded
     // with device-scope atomic maxima of IEEE bit patterns (values >= 0 or
@@ -457,7 +509,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
     const unsigned gsize = min((unsigned)kCflGroup, nwg - grp * kCflGroup);
     unsigned long long* gs = cflo.ws + (size_t)kCflSlot * (grp + 1);  // group slots
     unsigned long long* ts = cflo.ws;                                 // top slots
-    if (in_range && l == 0) {
+    if (lead) {
       const unsigned long long o1 = __hip_atomic_fetch_max(
           &gs[1], (unsigned long long)__double_as_longlong(lam_b), __ATOMIC_RELAXED,
           __HIP_MEMORY_SCOPE_AGENT);
@@ -473,7 +525,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
       unsigned long long dep = 0;
 #pragma unroll
       for (int k = 0; k < G::PPW; ++k)
-        if ((int64_t)blockIdx.x * G::PPW + k < count) dep |= dep_s[k];
+        if (wgi * G::PPW + k < count) dep |= dep_s[k];
       const unsigned long long before =
           __hip_atomic_fetch_add(&gs[0], 1ull + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       stage = before == gsize - 1 ? 1 : 0;
@@ -517,7 +569,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
 // ---------------------------------------------------------------------------
 constexpr int kMixedNT = 256;
 template <int P>
-constexpr int mixed_lds() { return Geo<3, P, kMixedNT>::PPW * Geo<3, P, kMixedNT>::SLOT; }
+constexpr int mixed_lds() { return Geo<3, P, kMixedNT, 1>::PPW * Geo<3, P, kMixedNT, 1>::SLOT; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // Two waves per SIMD: the union of the three bodies would otherwise take
@@ -539,19 +591,19 @@ fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
     if (un.first < 0 || un.count < 0 || un.first > n - un.count) continue;
     if (un.p == 16) {
       const int64_t b = un.count > 0 ? order[un.first] : -1;
-      update_body<T, 3, 16, kMixedNT, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
+      update_body<T, 3, 16, kMixedNT, 1, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
                                                       qout_len, 0, gamma, nullptr, max_eig, cfl,
                                                       b, lds, red);
     } else if (un.p == 8) {
       const int slot = tid / 64;
       const int64_t b = slot < un.count ? order[un.first + slot] : -1;
-      update_body<T, 3, 8, kMixedNT, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
+      update_body<T, 3, 8, kMixedNT, 1, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
                                                      qout_len, 0, gamma, nullptr, max_eig, cfl,
                                                      b, lds, red);
     } else if (un.p == 4) {
       const int slot = tid / 16;
       const int64_t b = slot < un.count ? order[un.first + slot] : -1;
-      update_body<T, 3, 4, kMixedNT, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
+      update_body<T, 3, 4, kMixedNT, 1, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
                                                      qout_len, 0, gamma, nullptr, max_eig, cfl,
                                                      b, lds, red);
     }
@@ -565,7 +617,7 @@ int launch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin,
            double* max_eig, const CflOut& cflo, const int64_t* order, int64_t order_base,
            int64_t count, hipStream_t st) {
   using G = Geo<D, P>;
-  static_assert(G::PPW * G::LANES <= G::NT, "workgroup too small");
+  static_assert(G::PPW * G::TPP <= G::NT, "workgroup too small");
   const int64_t blocks = (count + G::PPW - 1) / G::PPW;
   if (blocks == 0) return 0;
   const LaunchEvents& ev = launch_events();
@@ -651,9 +703,9 @@ int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighb
 }
 
 int mixed_patches_per_unit(int p) {
-  return p == 16 ? Geo<3, 16, kMixedNT>::PPW
-       : p == 8  ? Geo<3, 8, kMixedNT>::PPW
-       : p == 4  ? Geo<3, 4, kMixedNT>::PPW
+  return p == 16 ? Geo<3, 16, kMixedNT, 1>::PPW
+       : p == 8  ? Geo<3, 8, kMixedNT, 1>::PPW
+       : p == 4  ? Geo<3, 4, kMixedNT, 1>::PPW
                  : 0;
 }
 
