@@ -1,0 +1,208 @@
+"""Pins of the learned-correction oracle (oracle/learned.py) against things
+other than itself: the C oracle's plain update, torch's bfloat16 rounding,
+closed forms (uniform states, constant corrections, exact averages), the
+telescoping identity between fine and coarse updates, and finite
+differences of the loss."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as L
+from paper_2302_09005_amd import workloads as W
+
+EPS = 2.0 ** -52
+
+
+def _random_grid(n, seed, rho=(0.5, 1.5)):
+    rng = np.random.default_rng(seed)
+    shape = (n, n)
+    return W.to_conserved(rng.uniform(*rho, shape), [rng.uniform(-0.5, 0.5, shape) for _ in range(2)],
+                          rng.uniform(0.5, 2.0, shape))
+
+
+def _random_params(seed, scale=0.3, y_scale=1e-3):
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shape in L.BLOB_LAYOUT:
+        p[name] = rng.normal(0.0, scale, shape).astype(np.float32)
+    p["x_mean"] = rng.uniform(-0.5, 1.5, L.NF).astype(np.float32)
+    p["x_scale"] = rng.uniform(0.5, 2.0, L.NF).astype(np.float32)
+    p["y_scale"] = np.full(L.NO, y_scale, np.float32)
+    p["y_mean"] = np.zeros(L.NO, np.float32)
+    return p
+
+
+def test_bf16_rounding_values_and_torch():
+    import torch
+    x = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, -(1 + 2 ** -8),
+                  np.inf, -np.inf, 3.4e38, 1e-40, 0.0, -0.0], np.float32)
+    want = np.array([1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, -1.0, np.inf, -np.inf, np.inf],
+                    np.float32)
+    got = L.bf16_round(x)
+    np.testing.assert_array_equal(got[:8], want)
+    assert np.isnan(L.bf16_round(np.array([np.nan], np.float32)))[0]
+    rng = np.random.default_rng(0)
+    y = (rng.standard_normal(100000) * 10.0 ** rng.uniform(-30, 30, 100000)).astype(np.float32)
+    ref = torch.from_numpy(y).to(torch.bfloat16).float().numpy()
+    np.testing.assert_array_equal(L.bf16_round(y), ref)
+    np.testing.assert_array_equal(L.bf16_round(x), torch.from_numpy(x).to(torch.bfloat16).float().numpy())
+
+
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_plain_update_equals_c_oracle(bc):
+    """Without parameters the numpy update is the plain method: bit for bit the
+    C oracle's update of the same grid cut into 16^2 patches."""
+    q = _random_grid(64, 1)
+    counts = (4, 4)
+    grid = W.PatchGrid(2, 16, counts, 1.0 / 64, bc=(bc, bc))
+    dt = 2e-3
+    ref_flat, _ = oracle.fv_step(grid.offsets(), grid.offsets(), np.full((grid.n, 3), grid.dx),
+                                 np.full(grid.n, dt), grid.pack(q), 2, 16, out_halo=True,
+                                 out_len=grid.buffer_len(True))
+    got, _, _ = L.learned_step_2d(q, grid.dx, grid.dx, dt, None, bc)
+    np.testing.assert_array_equal(got, grid.unpack(ref_flat))
+
+
+def test_zero_network_is_the_plain_update():
+    q = _random_grid(32, 2)
+    p = _random_params(3)
+    for name in ("w1", "w2", "w3", "b1", "b2", "b3", "y_mean"):
+        p[name][...] = 0.0
+    a, Fa, Ga = L.learned_step_2d(q, 1 / 32, 1 / 32, 1e-3, p)
+    b, Fb, Gb = L.learned_step_2d(q, 1 / 32, 1 / 32, 1e-3, None)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(Fa, Fb)
+
+
+def test_constant_correction_closed_form():
+    """A network that outputs the constant c: every unflagged face gets dF = c
+    in the face frame (tangential and normal momenta swap on y faces), the
+    flagged ones none."""
+    q = W.to_conserved(np.where(np.arange(32)[None, :] < 16, 1.0, 0.5) * np.ones((32, 32)),
+                       [0.1, -0.2], 1.0)  # a density jump of 1 (indicator 1.0) at x = 16 and 0
+    p = _random_params(4)
+    for name in ("w1", "w2", "w3", "b1", "b2"):
+        p[name][...] = 0.0
+    c = np.array([0.25, -0.5, 0.75, 1.0], np.float32)
+    p["b3"][...] = c
+    p["y_scale"][...] = 1.0
+    p["y_mean"][...] = 0.0
+    _, Fx, Fy = L.learned_step_2d(q, 1 / 32, 1 / 32, 1e-3, p)
+    _, Px, Py = L.learned_step_2d(q, 1 / 32, 1 / 32, 1e-3, None)
+    dx, dy = Fx - Px, Fy - Py
+    flagged = np.zeros(Fx.shape[1:], bool)
+    flagged[:, 0] = flagged[:, 16] = flagged[:, 32] = True  # periodic: x = 0 and 32 see the jump
+    cx = c.astype(np.float64)[:, None, None]
+    cy = c.astype(np.float64)[[0, 2, 1, 3], None, None]
+    tol = 4 * EPS * (np.abs(Px) + 1)
+    assert (np.abs(np.where(flagged, dx, dx - cx)) <= tol).all()
+    assert (np.abs(dy - cy) <= 4 * EPS * (np.abs(Py) + 1)).all()
+
+
+def test_transposed_grid_gives_transposed_result():
+    q = _random_grid(24, 5)
+    p = _random_params(6)
+    a, _, _ = L.learned_step_2d(q, 1 / 24, 1 / 24, 2e-3, p)
+    qt = q[[0, 2, 1, 3]].transpose(0, 2, 1).copy()
+    b, _, _ = L.learned_step_2d(qt, 1 / 24, 1 / 24, 2e-3, p)
+    bt = b[[0, 2, 1, 3]].transpose(0, 2, 1)
+    assert np.abs(a - bt).max() <= 1e-14 * np.abs(a).max()
+
+
+def test_correction_changes_the_update_where_unflagged():
+    q = _random_grid(16, 7)
+    p = _random_params(8)
+    a, _, _ = L.learned_step_2d(q, 1 / 16, 1 / 16, 1e-3, p)
+    b, _, _ = L.learned_step_2d(q, 1 / 16, 1 / 16, 1e-3, None)
+    assert np.abs(a - b).max() > 1e-7
+
+
+def test_coarse_grain_closed_forms():
+    y, x = np.meshgrid(np.arange(64.0), np.arange(64.0), indexing="ij")
+    qf = np.stack([1.0 + 0 * x, x, y, x + 2 * y])
+    qc = L.coarse_grain(qf)
+    yc, xc = np.meshgrid(np.arange(16.0), np.arange(16.0), indexing="ij")
+    np.testing.assert_allclose(qc[1], 4 * xc + 1.5, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(qc[2], 4 * yc + 1.5, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(qc[0], 1.0)
+    qr = _random_grid(64, 9)
+    np.testing.assert_allclose(L.coarse_grain(qr).sum(axis=(1, 2)) * 16, qr.sum(axis=(1, 2)),
+                               rtol=1e-13)
+
+
+def test_uniform_state_fluxes_and_zero_targets():
+    q = W.to_conserved(np.full((32, 32), 0.7), [0.3, -0.1], 1.2)
+    f0, _ = L.euler_flux_2d(q, 0)
+    for k in (0, 1):
+        F = L.coarse_face_flux(q, k, "periodic")
+        fk, _ = L.euler_flux_2d(q[:, :1, :1], k)
+        assert np.abs(F - fk).max() <= 4 * EPS * np.abs(fk).max()
+    qc = L.coarse_grain(q)
+    feats, targ, ind = L.face_samples(qc, L.coarse_face_flux(q, 0, "periodic"),
+                                      L.coarse_face_flux(q, 1, "periodic"), "periodic")
+    assert np.abs(targ).max() <= 4 * EPS * np.abs(f0).max()
+    assert (ind == 0).all()
+    np.testing.assert_array_equal(feats[:, 0:4], feats[:, 4:8])
+
+
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_telescoping_fine_fluxes_reproduce_the_coarse_grained_update(bc):
+    """Four fine steps of dt on the 4x finer grid, coarse-grained, equal the
+    coarse state advanced by 4 dt with the time- and face-averaged fine
+    fluxes through the coarse faces (conservation, to rounding)."""
+    qf = _random_grid(64, 10)
+    dxf, dt = 1 / 64, 5e-4
+    Fx = Fy = 0.0
+    q = qf
+    for _ in range(4):
+        Fx = Fx + L.coarse_face_flux(q, 0, bc) / 4
+        Fy = Fy + L.coarse_face_flux(q, 1, bc) / 4
+        q, _, _ = L.learned_step_2d(q, dxf, dxf, dt, None, bc)
+    qc0, qc1 = L.coarse_grain(qf), L.coarse_grain(q)
+    dtc, dxc = 4 * dt, 4 * dxf
+    pred = qc0 - (dtc / dxc) * (Fx[:, :, 1:] - Fx[:, :, :-1]) - (dtc / dxc) * (Fy[:, 1:] - Fy[:, :-1])
+    assert np.abs(pred - qc1).max() <= 1e-13 * np.abs(qc1).max()
+    # and a wrong weight breaks it
+    bad = qc0 - (dtc / dxc) * 0.5 * (Fx[:, :, 1:] - Fx[:, :, :-1]) - (dtc / dxc) * (Fy[:, 1:] - Fy[:, :-1])
+    assert np.abs(bad - qc1).max() > 1e-6
+
+
+def test_loss_gradients_against_finite_differences():
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((40, 16))
+    y = rng.standard_normal((40, 4)) * 0.5
+    p = {k: v.astype(np.float64) for k, v in _random_params(12, scale=0.4).items()}
+    loss, g = L.mlp_loss_grads(x, y, p)
+    for name, idx in (("w1", (3, 5)), ("b1", (7,)), ("w2", (10, 20)), ("b2", (1,)),
+                      ("w3", (2, 33)), ("b3", (3,))):
+        h = 1e-6
+        pp = {k: v.copy() for k, v in p.items()}
+        pp[name][idx] += h
+        lp, _ = L.mlp_loss_grads(x, y, pp)
+        pp[name][idx] -= 2 * h
+        lm, _ = L.mlp_loss_grads(x, y, pp)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[name][idx]) <= 1e-7 * max(1.0, abs(fd)), (name, fd, g[name][idx])
+
+
+def test_adam_matches_the_published_first_step():
+    """Adam's first step moves every parameter by lr * sign(grad) (bias
+    correction makes m_hat / sqrt(v_hat) = g / |g|), up to eps."""
+    p = {k: np.ones((2, 2), np.float32) for k in ("w1", "b1", "w2", "b2", "w3", "b3")}
+    g = {k: np.array([[0.5, -2.0], [1e-3, -7.0]]) for k in p}
+    m = {k: np.zeros((2, 2)) for k in p}
+    v = {k: np.zeros((2, 2)) for k in p}
+    L.adam_update(p, g, m, v, 1, 0.01)
+    for k in p:
+        np.testing.assert_allclose(p[k], 1.0 - 0.01 * np.sign(g[k]), rtol=0, atol=1e-5)
+
+
+def test_blob_layout_round_trip():
+    p = _random_params(13)
+    blob = L.pack_blob(p)
+    assert blob.size == L.BLOB_SIZE == 5548
+    q = L.unpack_blob(blob)
+    for k in p:
+        np.testing.assert_array_equal(q[k], p[k])
