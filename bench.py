@@ -402,6 +402,75 @@ def sweep_2d_p17(seed, ns, reps):
         print(json.dumps(row), flush=True)
 
 
+def learned_path(seed, train_seeds=(101, 102, 103), coarse_steps=8, epochs=20,
+                 max_samples=200000):
+    """The learned face-flux correction on 2-D Euler, 256 patches of 16^2:
+    samples from 4x finer plain runs of seeded Riemann problems (faces with
+    density-jump indicator <= 0.2), minibatch-Adam training, then a held-out
+    problem run coarse with the plain and the corrected update against the
+    coarse-grained fine run; plus the time of one corrected update launch
+    against the plain gather update on the same patches."""
+    import time as _time
+    import torch
+    from paper_2302_09005_amd import fv, learned
+    from paper_2302_09005_amd import workloads as W
+    t0 = _time.perf_counter()
+    feats, targs = [], []
+    for sd in train_seeds:
+        (f, t), _, _ = learned.fine_run(sd, coarse_steps)
+        feats.append(f)
+        targs.append(t)
+    f = torch.cat(feats)
+    t = torch.cat(targs)
+    n_all = f.shape[0]
+    if n_all > max_samples:
+        pick = torch.from_numpy(np.random.default_rng(seed).choice(n_all, max_samples,
+                                                                   replace=False)).cuda()
+        f, t = f[pick].contiguous(), t[pick].contiguous()
+    torch.cuda.synchronize()
+    t1 = _time.perf_counter()
+    blob, losses = learned.train(f, t, epochs=epochs, batch=1024, lr=1e-3, seed=seed)
+    torch.cuda.synchronize()
+    t2 = _time.perf_counter()
+    ev = learned.evaluate(blob, 200 + seed, coarse_steps)
+    # kernel times on the coarse workload
+    grid, q = W.grid_riemann_2d(learned.COARSE, learned.P, 200 + seed)
+    run = learned.PatchRun(grid, q)
+    dt = run.cfl_dt(learned.CFL)
+    reps = 20
+
+    def timed(fn):
+        hip = HipEvents(reps)
+        for i in range(reps):
+            fv.set_launch_events(hip.start[i], hip.stop[i])
+            fn()
+        fv.set_launch_events(None, None)
+        torch.cuda.synchronize()
+        us = float(np.median(hip.elapsed_ms()) * 1e3)
+        hip.destroy()
+        return us
+
+    for _ in range(3):
+        run.step_plain(dt)
+        run.step_learned(dt, blob)
+    plain_us = timed(lambda: run.step_plain(dt))
+    learned_us = timed(lambda: run.step_learned(dt, blob))
+    faces = 2 * 17 * 16 * grid.n
+    flops = faces * 2 * (16 * 64 + 64 * 64 + 64 * 4)
+    last = {k: v[-1] for k, v in ev.items()}
+    return {"workload": "2d-euler-256x16^2-riemann, 4x finer reference runs",
+            "samples": int(n_all), "samples_used": int(f.shape[0]),
+            "train_seeds": list(train_seeds), "coarse_steps": coarse_steps, "epochs": epochs,
+            "loss_first_last": [losses[0], losses[-1]],
+            "data_s": t1 - t0, "train_s": t2 - t1,
+            "eval_seed": 200 + seed,
+            "l1_error_after_steps": {"plain": last["plain"], "learned": last["learned"]},
+            "l1_rho_per_step": {"plain": [e[0] for e in ev["plain"]],
+                                "learned": [e[0] for e in ev["learned"]]},
+            "plain_update_us": plain_us, "learned_update_us": learned_us,
+            "mlp_tflops": flops / (learned_us * 1e-6) / 1e12}
+
+
 def copy_calibration(mib=1024, reps=5):
     """Plain device copy of a known size, for scaling rocprofv3 byte counters."""
     import torch
@@ -424,6 +493,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-batch detail (20 000 mixed-size patches)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned face-flux correction detail")
     ap.add_argument("--sweep-2d-p17", action="store_true",
                     help="only run the 2-D p=17 sweep over N patches per call (one JSON line per N)")
     ap.add_argument("--uneven-schedule", default=None, metavar="SCHED:WG",
@@ -530,6 +601,8 @@ def main():
         uneven32 = uneven_path(args.seed, dtype=np.float32, tune=False,
                                schedule=tuple(uneven["schedule"]["chosen"]))
 
+    learned_detail = None if args.no_learned else learned_path(args.seed)
+
     cells = grid.cells
     value = cells * args.steps / (total_ms * 1e-3)
     bpc = algorithmic_bytes_per_cell(d, p, s, 8)
@@ -566,7 +639,8 @@ def main():
                    "plain_halo_path": plain,
                    "fp32_path": f32,
                    "uneven_batch": uneven,
-                   "uneven_batch_fp32": uneven32},
+                   "uneven_batch_fp32": uneven32,
+                   "learned_flux": learned_detail},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid, grid.pack(q), args.cpu_budget, 100)

@@ -313,6 +313,91 @@ int fv_local_timestep(fv_patch* patches, int64_t n_patches, const double* per_pa
                       int dim, double cfl, void* stream);
 
 /*
+ * ---------------------------------------------------------------------------
+ * Learned face-flux correction (2-D Euler, s = 4).  Not in the paper: an
+ * extension of its Rusanov update (Section 2, eqs. (2)-(5)) in which a small
+ * network adds a correction to each face flux.
+ *
+ * Face frame: a face with normal along axis k lies between volumes i-1 (L)
+ * and i (R) along k; states are read as (rho, j_n, j_t, E).  Features: the
+ * volumes i-2, i-1, i, i+1 in that frame, 16 values, normalised as
+ * (x - x_mean) * x_scale.  Network 16 -> 64 -> 64 -> 4 with tanh on the
+ * hidden layers; the products take bfloat16 operands (weights and
+ * activations rounded to nearest even) with float32 sums.  Correction
+ * dF = o * y_scale + y_mean in the face frame, rotated back; 0 where
+ * |rho_R - rho_L| / min(rho_L, rho_R) > threshold (plain Rusanov there).
+ *
+ * Parameter blob: device float32[5548]: x_mean[16], x_scale[16], W1[64][16],
+ * b1[64], W2[64][64], b2[64], W3[4][64], b3[4], y_scale[4], y_mean[4]
+ * (float32 master values; inference rounds the weights to bfloat16).
+ *
+ * Regular patch grids (training-data entry points): npx x npy patches of
+ * p x p volumes, compact blocks [4][p][p] back to back in patch order (x
+ * fastest); bc 0 periodic, 1 transmissive (zero gradient).
+ * ---------------------------------------------------------------------------
+ */
+#define FV_MLP_BLOB_WORDS 5548
+#define FV_MLP_TRAINED_WORDS 5508   /* W1, b1, W2, b2, W3, b3 */
+
+/* acc_x[4][ncy][ncx+1] and acc_y[4][ncy+1][ncx] (device float64, coarse grid
+ * ncx = npx*p/r, ncy = npy*p/r) += weight * (mean over the r fine faces of
+ * each coarse face of the fine Rusanov flux of q_fine).  Called once per fine
+ * step with weight 1/r, it builds the time- and face-averaged fine flux of
+ * one coarse step (r fine steps).  r must divide p. */
+int fv_learned_flux_accumulate(const double* q_fine, int npx, int npy, int p, int r, int bc,
+                               double gamma, double weight, double* acc_x, double* acc_y,
+                               void* stream);
+
+/* Conservative r x r averages: q_coarse is the regular grid of npx/r x npy/r
+ * patches of the same p (npx, npy multiples of r). */
+int fv_learned_coarse_grain(const double* q_fine, int npx, int npy, int p, int r,
+                            double* q_coarse, void* stream);
+
+/* One sample per face of the coarse grid (x faces [ncy][ncx+1] then y faces
+ * [ncy+1][ncx], row-major): features[n][16], targets[n][4] (face-frame
+ * acc - Rusanov flux of the coarse state) and indicator[n], all float32. */
+int fv_learned_face_samples(const double* q_coarse, int npx, int npy, int p, int bc,
+                            double gamma, const double* acc_x, const double* acc_y,
+                            float* features, float* targets, float* indicator, void* stream);
+
+/* Per-column mean and spread of x[x_rows][cols] over the n_rows rows listed
+ * in rows (device int64; NULL: all x_rows rows; a listed row outside
+ * [0, x_rows) counts as zeros): mean_out[c]; scale_out[c] = 1/std (mode 0,
+ * features) or std (mode 1, targets).  Pointers may address the blob's
+ * x_mean/x_scale or y_mean/y_scale slots. */
+int fv_mlp_fit_normalization(const float* x, int64_t x_rows, int cols, int mode,
+                             const int64_t* rows, int64_t n_rows, float* mean_out,
+                             float* scale_out, void* stream);
+
+/* One Adam step (lr, step >= 1 counts steps) on the minibatch of rows
+ * batch_idx[batch] (in [0, n_rows); other indices contribute nothing) of
+ * (features[n_rows][16], targets[n_rows][4]): float32 forward and backward of
+ * the mean-squared error of normalised targets, gradients summed in a fixed
+ * order (deterministic).  adam: device float32[2 * 5508] moments (zero at
+ * step 1); workspace: float32[fv_mlp_workspace_words(batch)];
+ * grad_out: float32[5508] or NULL (the gradient of W1..b3). */
+int fv_mlp_workspace_words(int batch);
+int fv_mlp_train_step(float* blob, float* adam, int step, float lr, const float* features,
+                      const float* targets, int64_t n_rows, const int64_t* batch_idx, int batch,
+                      float* workspace, int64_t workspace_words, float* grad_out, void* stream);
+
+/* Network outputs o[n][4] (before y_scale / y_mean) for raw features[n][16],
+ * computed the way the fused update does (bfloat16 matrix-core products). */
+int fv_mlp_forward(const float* blob, const float* features, int64_t n, float* out,
+                   void* stream);
+
+/* One explicit step of 2-D patches of 16 x 16 volumes with corrected face
+ * fluxes.  Compact blocks, halo of two volumes read from the face neighbours
+ * (neighbours[n][4]: -x, +x, -y, +y; -1 = transmissive, which repeats the
+ * boundary volume).  dt from dt_dev (device) or, when NULL, each descriptor.
+ * max_eig (device, optional): largest |u_k| + c of each new patch. */
+int fv_batch_update_learned_2d(const fv_patch* patches, int64_t n_patches,
+                               const int64_t* neighbours, const double* q_in, int64_t q_in_len,
+                               double* q_out, int64_t q_out_len, double gamma,
+                               const double* dt_dev, const float* blob, double threshold,
+                               double* max_eig, void* stream);
+
+/*
  * fv_max_eigenvalue -- largest eigenvalue of a given state (Section 2,
  * eq. (5); Algorithm 1 last step), for the first CFL step of a run.
  *

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libfv.so")
-SOURCES = ["fv_api.hip", "fv_update.hip", "fv_reduce.hip", "fv_halo.hip"]
+SOURCES = ["fv_api.hip", "fv_update.hip", "fv_reduce.hip", "fv_halo.hip", "fv_learned_train.hip",
+           "fv_learned_infer.hip"]
 ARCH = os.environ.get("FV_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -494,3 +494,117 @@ int fv_fill_halo(const fv_patch* patches, int64_t n, const int64_t* neighbours, 
 }
 
 }  // extern "C"
+
+namespace {
+
+// ---- learned face-flux correction ------------------------------------------
+
+int check_grid2(int npx, int npy, int p, int r, int bc) {
+  if (npx < 1 || npy < 1 || p < 1) return fail(FV_EINVAL, "empty patch grid");
+  if (r < 1 || p % r != 0) return fail(FV_EINVAL, "r must divide p (p=%d r=%d)", p, r);
+  if (bc != 0 && bc != 1) return fail(FV_EINVAL, "bc must be 0 (periodic) or 1 (transmissive)");
+  if ((int64_t)npx * npy * p * p > ((int64_t)1 << 31)) return fail(FV_EINVAL, "grid too large");
+  return FV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fv_learned_flux_accumulate(const double* q_fine, int npx, int npy, int p, int r, int bc,
+                               double gamma, double weight, double* acc_x, double* acc_y,
+                               void* stream) {
+  int rc = check_grid2(npx, npy, p, r, bc);
+  if (rc) return rc;
+  if (!q_fine || !acc_x || !acc_y) return fail(FV_EINVAL, "null device pointer");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  fvk::launch_face_flux_accumulate(q_fine, npx, npy, p, r, bc, gamma, weight, acc_x, acc_y,
+                                   (hipStream_t)stream);
+  return launched("fv_learned_flux_accumulate");
+}
+
+int fv_learned_coarse_grain(const double* q_fine, int npx, int npy, int p, int r,
+                            double* q_coarse, void* stream) {
+  int rc = check_grid2(npx, npy, p, r, 0);
+  if (rc) return rc;
+  if (npx % r || npy % r) return fail(FV_EINVAL, "npx and npy must be multiples of r");
+  if (!q_fine || !q_coarse) return fail(FV_EINVAL, "null device pointer");
+  if (q_fine == q_coarse) return fail(FV_EINVAL, "q_coarse must not alias q_fine");
+  fvk::launch_coarse_grain(q_fine, npx, npy, p, r, q_coarse, (hipStream_t)stream);
+  return launched("fv_learned_coarse_grain");
+}
+
+int fv_learned_face_samples(const double* q_coarse, int npx, int npy, int p, int bc,
+                            double gamma, const double* acc_x, const double* acc_y,
+                            float* features, float* targets, float* indicator, void* stream) {
+  int rc = check_grid2(npx, npy, p, 1, bc);
+  if (rc) return rc;
+  if (!q_coarse || !acc_x || !acc_y || !features || !targets || !indicator)
+    return fail(FV_EINVAL, "null device pointer");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  fvk::launch_face_samples(q_coarse, npx, npy, p, bc, gamma, acc_x, acc_y, features, targets,
+                           indicator, (hipStream_t)stream);
+  return launched("fv_learned_face_samples");
+}
+
+int fv_mlp_fit_normalization(const float* x, int64_t x_rows, int cols, int mode,
+                             const int64_t* rows, int64_t n_rows, float* mean_out,
+                             float* scale_out, void* stream) {
+  const int64_t n = rows ? n_rows : x_rows;
+  if (x_rows < 1 || n < 1 || cols < 1 || cols > 65535) return fail(FV_EINVAL, "bad sizes");
+  if (mode != 0 && mode != 1) return fail(FV_EINVAL, "mode must be 0 or 1");
+  if (!x || !mean_out || !scale_out) return fail(FV_EINVAL, "null device pointer");
+  fvk::launch_column_stats(x, x_rows, n, cols, mode, rows, mean_out, scale_out,
+                           (hipStream_t)stream);
+  return launched("fv_mlp_fit_normalization");
+}
+
+int fv_mlp_workspace_words(int batch) { return batch < 1 ? 0 : fvk::mlp_workspace_words(batch); }
+
+int fv_mlp_train_step(float* blob, float* adam, int step, float lr, const float* features,
+                      const float* targets, int64_t n_rows, const int64_t* batch_idx, int batch,
+                      float* workspace, int64_t workspace_words, float* grad_out, void* stream) {
+  if (n_rows < 1) return fail(FV_EINVAL, "n_rows must be >= 1");
+  if (batch < 1 || batch > (1 << 20)) return fail(FV_EINVAL, "batch must be in [1, 2^20]");
+  if (step < 1) return fail(FV_EINVAL, "step counts from 1");
+  if (!(lr > 0.0f) || !isfinite(lr)) return fail(FV_EINVAL, "lr must be finite and > 0");
+  if (!blob || !adam || !features || !targets || !batch_idx || !workspace)
+    return fail(FV_EINVAL, "null device pointer");
+  if (workspace_words < fvk::mlp_workspace_words(batch))
+    return fail(FV_EINVAL, "workspace needs %d words", fvk::mlp_workspace_words(batch));
+  fvk::launch_mlp_train_step(blob, adam, step, lr, features, targets, n_rows, batch_idx, batch,
+                             workspace, grad_out, (hipStream_t)stream);
+  return launched("fv_mlp_train_step");
+}
+
+int fv_mlp_forward(const float* blob, const float* features, int64_t n, float* out,
+                   void* stream) {
+  if (n < 0) return fail(FV_EINVAL, "n < 0");
+  if (n == 0) return ok();
+  if (!blob || !features || !out) return fail(FV_EINVAL, "null device pointer");
+  if (n > ((int64_t)1 << 31)) return fail(FV_EINVAL, "too many samples");
+  fvk::launch_mlp_forward(blob, features, n, out, (hipStream_t)stream);
+  return launched("fv_mlp_forward");
+}
+
+int fv_batch_update_learned_2d(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                               const double* q_in, int64_t q_in_len, double* q_out,
+                               int64_t q_out_len, double gamma, const double* dt_dev,
+                               const float* blob, double threshold, double* max_eig,
+                               void* stream) {
+  if (n < 0) return fail(FV_EINVAL, "n_patches < 0");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (!(threshold >= 0.0)) return fail(FV_EINVAL, "threshold must be >= 0");
+  if (n == 0) return ok();
+  if (!patches || !neighbours || !q_in || !q_out || !blob)
+    return fail(FV_EINVAL, "null device pointer");
+  if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  int rc = overlap_check(q_in, q_in_len, q_out, q_out_len);
+  if (rc) return rc;
+  fvk::launch_update_learned_2d(patches, n, neighbours, q_in, q_in_len, q_out, q_out_len, gamma,
+                                dt_dev, blob, threshold, max_eig, (hipStream_t)stream);
+  return launched("fv_batch_update_learned_2d");
+}
+
+}  // extern "C"

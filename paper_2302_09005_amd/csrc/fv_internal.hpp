@@ -148,4 +148,28 @@ int launch_fill_halo_f64(const fv_patch* patches, int64_t n, const int64_t* neig
 
 bool update_supported(int dim, int p);
 
+// Learned face-flux correction (2-D): training data, training, inference.
+int launch_face_flux_accumulate(const double* qf, int npx, int npy, int p, int r, int bc,
+                                double gamma, double weight, double* accx, double* accy,
+                                hipStream_t st);
+int launch_coarse_grain(const double* qf, int npx, int npy, int p, int r, double* qc,
+                        hipStream_t st);
+int launch_face_samples(const double* qc, int npx, int npy, int p, int bc, double gamma,
+                        const double* accx, const double* accy, float* feats, float* targ,
+                        float* ind, hipStream_t st);
+int launch_column_stats(const float* x, int64_t x_rows, int64_t n, int cols, int mode,
+                        const int64_t* rows, float* mean, float* scale, hipStream_t st);
+int mlp_blob_words();
+int mlp_trained_words();
+int mlp_workspace_words(int batch);
+int launch_mlp_train_step(float* blob, float* adam, int step, float lr, const float* feats,
+                          const float* targ, int64_t n_rows, const int64_t* idx, int batch,
+                          float* ws, float* grad_out, hipStream_t st);
+int launch_mlp_forward(const float* blob, const float* feats, int64_t n, float* out,
+                       hipStream_t st);
+int launch_update_learned_2d(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                             const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
+                             double gamma, const double* dt_dev, const float* blob,
+                             double threshold, double* max_eig, hipStream_t st);
+
 }  // namespace fvk

@@ -1,0 +1,360 @@
+// Learned face-flux correction, 2-D Euler: inference.  The per-face network
+// (16 -> 64 -> 64 -> 4, tanh) runs on the matrix cores: one wave evaluates 64
+// faces at a time as three bfloat16 products with float32 sums
+// (v_mfma_f32_32x32x16_bf16: a 32 x 16 by 16 x 32 product per instruction;
+// layer 1 is 2 x 2 instructions, layer 2 2 x 2 x 4, layer 3 2 x 1 x 4 with
+// the four outputs padded to 32 columns).  The fused update keeps a patch of
+// 16 x 16 volumes and its two-volume face halo in LDS, evaluates all 544
+// faces (Rusanov flux in float64 plus the correction), then updates every
+// volume from its four face fluxes.
+#include <math.h>
+
+#include "fv_euler.hpp"
+#include "fv_internal.hpp"
+
+namespace fvk {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kNF = 16, kNH = 64, kNO = 4;
+constexpr int kXM = 0, kXS = 16, kW1 = 32, kB1 = kW1 + kNH * kNF, kW2 = kB1 + kNH,
+              kB2 = kW2 + kNH * kNH, kW3 = kB2 + kNH, kB3 = kW3 + kNO * kNH, kYS = kB3 + kNO,
+              kYM = kYS + kNO;
+
+// float32 -> bfloat16 bits, round to nearest even; NaN stays NaN.
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  const unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Matrix-core lane layout of the 32 x 32 x 16 product (wave64): lane l holds
+// A[l % 32][8 (l / 32) + e] and B[8 (l / 32) + e][l % 32] for e = 0..7, and
+// accumulator register r holds C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+__device__ __forceinline__ int acc_row(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+
+struct MlpFrags {
+  bf16x8 w1[2];      // [col tile]
+  bf16x8 w2[2][4];   // [col tile][k step]
+  bf16x8 w3[4];      // [k step], columns >= 4 zero
+  float b1[2], b2[2], b3;  // biases of this lane's columns
+};
+
+__device__ __forceinline__ bf16x8 frag_from(const float* row, bool valid) {
+  bf16x8 f;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const unsigned short h = valid ? bf16_bits(row[e]) : (unsigned short)0;
+    f[e] = __builtin_bit_cast(__bf16, h);
+  }
+  return f;
+}
+
+__device__ MlpFrags load_frags(const float* __restrict__ blob, int l) {
+  MlpFrags F;
+  const int j = l & 31, kh = 8 * (l >> 5);
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    F.w1[ct] = frag_from(blob + kW1 + (32 * ct + j) * kNF + kh, true);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+      F.w2[ct][ks] = frag_from(blob + kW2 + (32 * ct + j) * kNH + 16 * ks + kh, true);
+    F.b1[ct] = blob[kB1 + 32 * ct + j];
+    F.b2[ct] = blob[kB2 + 32 * ct + j];
+  }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+    F.w3[ks] = frag_from(blob + kW3 + (j < kNO ? j : 0) * kNH + 16 * ks + kh, j < kNO);
+  F.b3 = j < kNO ? blob[kB3 + j] : 0.0f;
+  return F;
+}
+
+// Per-wave LDS scratch of the network.
+struct MlpLds {
+  alignas(16) unsigned short x[64 * kNF];   // bfloat16 inputs [face][feature]
+  alignas(16) unsigned short h[64 * kNH];   // bfloat16 hidden layer [face][unit]
+  float o[64 * kNO];            // outputs [face][output]
+};
+
+// The network on the 64 faces of this wave: lane l holds the normalised
+// features xh[16] of face l and receives its outputs o[4].  Wave-local: the
+// LDS traffic of one wave is ordered, so no workgroup barrier is needed.
+__device__ void mlp64(const MlpFrags& F, MlpLds& s, int l, const float (&xh)[kNF],
+                      float (&o)[kNO]) {
+  const int j = l & 31, kh = 8 * (l >> 5);
+#pragma unroll
+  for (int k = 0; k < kNF; ++k) s.x[l * kNF + k] = bf16_bits(xh[k]);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // layer 1
+  bf16x8 a1[2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) a1[rt] = *reinterpret_cast<const bf16x8*>(&s.x[(32 * rt + j) * kNF + kh]);
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      floatx16 c = {};
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[rt], F.w1[ct], c, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        s.h[(32 * rt + acc_row(l, r)) * kNH + 32 * ct + j] = bf16_bits(tanhf(c[r] + F.b1[ct]));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // layer 2 (all of h1 is read before h2 overwrites it)
+  bf16x8 a2[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+      a2[rt][ks] = *reinterpret_cast<const bf16x8*>(&s.h[(32 * rt + j) * kNH + 16 * ks + kh]);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      floatx16 c = {};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[rt][ks], F.w2[ct][ks], c, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        s.h[(32 * rt + acc_row(l, r)) * kNH + 32 * ct + j] = bf16_bits(tanhf(c[r] + F.b2[ct]));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // layer 3
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    floatx16 c = {};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&s.h[(32 * rt + j) * kNH + 16 * ks + kh]);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, F.w3[ks], c, 0, 0, 0);
+    }
+    if (j < kNO) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s.o[(32 * rt + acc_row(l, r)) * kNO + j] = c[r] + F.b3;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+  for (int m = 0; m < kNO; ++m) o[m] = s.o[l * kNO + m];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Network outputs for raw feature rows (one wave per 64 rows).
+__global__ void __launch_bounds__(64)
+mlp_forward_kernel(const float* __restrict__ blob, const float* __restrict__ feats, int64_t n,
+                   float* __restrict__ out) {
+  __shared__ MlpLds s;
+  const int l = threadIdx.x;
+  const int64_t row = (int64_t)blockIdx.x * 64 + l;
+  const MlpFrags F = load_frags(blob, l);
+  const int64_t rr = row < n ? row : n - 1;
+  float xh[kNF], o[kNO];
+#pragma unroll
+  for (int k = 0; k < kNF; ++k) xh[k] = (feats[rr * kNF + k] - blob[kXM + k]) * blob[kXS + k];
+  mlp64(F, s, l, xh, o);
+  if (row < n) {
+#pragma unroll
+    for (int m = 0; m < kNO; ++m) out[row * kNO + m] = o[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused update of 2-D patches of 16 x 16 volumes with corrected fluxes.
+// ---------------------------------------------------------------------------
+constexpr int kP = 16, kH = 2, kW = kP + 2 * kH;  // volumes per axis with the halo
+constexpr int kNXF = (kP + 1) * kP;              // x faces (= y faces) per patch
+constexpr int kNFACE = 2 * kNXF;                 // 544
+constexpr int kThreads = 256;
+
+struct PatchLds {
+  double q[4][kW][kW];        // state with a two-volume face halo (corners unused)
+  double fx[4][kP][kP + 1];   // x-face fluxes [m][y][face x]
+  double fy[4][kP + 1][kP];   // y-face fluxes [m][face y][x]
+  double red[kThreads / 64];
+  MlpLds mlp[kThreads / 64];
+};
+
+__global__ void __launch_bounds__(kThreads)
+learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
+                      const int64_t* __restrict__ neighbours, const double* __restrict__ qin,
+                      int64_t qin_len, double* __restrict__ qout, int64_t qout_len,
+                      double gamma, const double* __restrict__ dt_dev,
+                      const float* __restrict__ blob, double threshold,
+                      double* __restrict__ max_eig) {
+  __shared__ PatchLds s;
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+  const int64_t b = blockIdx.x;
+  constexpr int64_t blk = 4 * kP * kP;
+  // descriptor and neighbour checks (the same in every thread)
+  const fv_patch pd = patches[b];
+  bool ok = pd.p == kP && pd.q_in >= 0 && pd.q_in <= qin_len - blk && pd.q_out >= 0 &&
+            pd.q_out <= qout_len - blk;
+  int64_t nbo[4];
+  for (int f = 0; f < 4; ++f) {
+    const int64_t nb = neighbours[b * 4 + f];
+    nbo[f] = -1;
+    if (nb >= 0 && nb < n) {
+      const fv_patch& pn = patches[nb];
+      if (pn.p == kP && pn.q_in >= 0 && pn.q_in <= qin_len - blk) nbo[f] = pn.q_in;
+      else ok = false;
+    } else if (nb != -1) {
+      ok = false;
+    }
+  }
+  if (!ok) {
+    if (tid == 0 && max_eig) max_eig[b] = __builtin_nan("");
+    return;  // uniform: the whole workgroup leaves
+  }
+  const double dt = dt_dev ? *dt_dev : pd.dt;
+  const double rx = dt / pd.dx[0], ry = dt / pd.dx[1];
+
+  // ---- state and face halo into LDS --------------------------------------
+  {
+    const int x = tid & 15, y = tid >> 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s.q[m][y + kH][x + kH] = qin[pd.q_in + m * kP * kP + y * kP + x];
+  }
+  if (tid < 128) {
+    // halo volume: side (-x, +x, -y, +y) and 32 per side (2 layers x 16)
+    const int side = tid >> 5, t = tid & 31, layer = t >> 4, pos = t & 15;
+    int hx, hy, sx, sy;  // LDS coordinates and source coordinates in the source block
+    int64_t src = pd.q_in;
+    if (side == 0) {        // x = -2 + layer
+      hx = layer; hy = pos + kH;
+      sx = nbo[0] >= 0 ? kP - 2 + layer : 0; sy = pos;
+      if (nbo[0] >= 0) src = nbo[0];
+    } else if (side == 1) { // x = 16 + layer
+      hx = kP + kH + layer; hy = pos + kH;
+      sx = nbo[1] >= 0 ? layer : kP - 1; sy = pos;
+      if (nbo[1] >= 0) src = nbo[1];
+    } else if (side == 2) { // y = -2 + layer
+      hx = pos + kH; hy = layer;
+      sx = pos; sy = nbo[2] >= 0 ? kP - 2 + layer : 0;
+      if (nbo[2] >= 0) src = nbo[2];
+    } else {                // y = 16 + layer
+      hx = pos + kH; hy = kP + kH + layer;
+      sx = pos; sy = nbo[3] >= 0 ? layer : kP - 1;
+      if (nbo[3] >= 0) src = nbo[3];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s.q[m][hy][hx] = qin[src + m * kP * kP + sy * kP + sx];
+  }
+  __syncthreads();
+
+  // ---- faces: 9 batches of 64 over the 4 waves ---------------------------
+  const MlpFrags F = load_frags(blob, l);
+  for (int batch = wave; batch * 64 < kNFACE; batch += kThreads / 64) {
+    const int f = batch * 64 + l;
+    const bool real = f < kNFACE;
+    const int ff = real ? f : kNFACE - 1;
+    const bool xdir = ff < kNXF;
+    const int g = xdir ? ff : ff - kNXF;
+    // face between volumes (i-1) and i along the normal; (fi, fj) in LDS
+    int I, J;
+    if (xdir) { I = g % (kP + 1); J = g / (kP + 1); }
+    else { I = g % kP; J = g / kP; }
+    double v[4][4];  // stencil volumes -2..+1, grid-axis components
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      const int cx = xdir ? I - 2 + o + kH : I + kH;
+      const int cy = xdir ? J + kH : J - 2 + o + kH;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) v[o][m] = s.q[m][cy][cx];
+    }
+    const int tn = xdir ? 1 : 2, tt = xdir ? 2 : 1;
+    float xh[kNF];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      const double fr[4] = {v[o][0], xdir ? v[o][1] : v[o][2], xdir ? v[o][2] : v[o][1], v[o][3]};
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        xh[4 * o + c] = ((float)fr[c] - blob[kXM + 4 * o + c]) * blob[kXS + 4 * o + c];
+    }
+    float out[kNO];
+    mlp64(F, s.mlp[wave], l, xh, out);
+    // plain flux of the face, grid axes
+    double Fr[4];
+    {
+      const Prim<double> wl = decode<double, 2>(v[1], gamma);
+      const Prim<double> wr = decode<double, 2>(v[2], gamma);
+      if (xdir) rusanov<double, 2, 0>(v[1], wl, v[2], wr, Fr);
+      else rusanov<double, 2, 1>(v[1], wl, v[2], wr, Fr);
+    }
+    const double ind = fabs(v[2][0] - v[1][0]) / fmin(v[1][0], v[2][0]);
+    const bool corr = !(ind > threshold);
+    double dfr[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dfr[c] = corr ? (double)(out[c] * blob[kYS + c] + blob[kYM + c]) : 0.0;
+    const double dF[4] = {dfr[0], xdir ? dfr[1] : dfr[2], xdir ? dfr[2] : dfr[1], dfr[3]};
+    (void)tn;
+    (void)tt;
+    if (real) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double flux = 0.5 * Fr[m] + dF[m];  // rusanov gives 2F
+        if (xdir) s.fx[m][J][I] = flux;
+        else s.fy[m][J][I] = flux;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- update, new-state maximum ----------------------------------------
+  const int x = tid & 15, y = tid >> 4;
+  double qn[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double v = s.q[m][y + kH][x + kH] - rx * (s.fx[m][y][x + 1] - s.fx[m][y][x]);
+    v = v - ry * (s.fy[m][y + 1][x] - s.fy[m][y][x]);
+    qn[m] = v;
+    qout[pd.q_out + m * kP * kP + y * kP + x] = v;
+  }
+  const Prim<double> wn = decode<double, 2>(qn, gamma);
+  double lam = max_wave_speed<double, 2>(qn, wn);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lam = nanmax_pos(lam, __shfl_xor(lam, o, 64));
+  if (l == 0) s.red[wave] = lam;
+  __syncthreads();
+  if (tid == 0 && max_eig) {
+    double mx = s.red[0];
+    for (int w = 1; w < kThreads / 64; ++w) mx = nanmax_pos(mx, s.red[w]);
+    max_eig[b] = mx;
+  }
+}
+
+}  // namespace
+
+int launch_mlp_forward(const float* blob, const float* feats, int64_t n, float* out,
+                       hipStream_t st) {
+  const int64_t blocks = (n + 63) / 64;
+  if (blocks == 0) return 0;
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)blocks), dim3(64), 0, st, blob, feats, n,
+                     out);
+  return 0;
+}
+
+int launch_update_learned_2d(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                             const double* qin, int64_t qin_len, double* qout, int64_t qout_len,
+                             double gamma, const double* dt_dev, const float* blob,
+                             double threshold, double* max_eig, hipStream_t st) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(learned_update_kernel, dim3((unsigned)n), dim3(kThreads), 0, st, patches, n,
+                     neighbours, qin, qin_len, qout, qout_len, gamma, dt_dev, blob, threshold,
+                     max_eig);
+  return 0;
+}
+
+}  // namespace fvk

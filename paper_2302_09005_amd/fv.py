@@ -104,6 +104,21 @@ def library():
         getattr(lib, name).restype = i32
     lib.fv_local_timestep.argtypes = [vp, i64, vp, i32, f64, vp]
     lib.fv_local_timestep.restype = i32
+    lib.fv_learned_flux_accumulate.argtypes = [vp, i32, i32, i32, i32, i32, f64, f64, vp, vp,
+                                               vp]
+    lib.fv_learned_coarse_grain.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+    lib.fv_learned_face_samples.argtypes = [vp, i32, i32, i32, i32, f64, vp, vp, vp, vp, vp, vp]
+    lib.fv_mlp_fit_normalization.argtypes = [vp, i64, i32, i32, vp, i64, vp, vp, vp]
+    lib.fv_mlp_workspace_words.argtypes = [i32]
+    lib.fv_mlp_train_step.argtypes = [vp, vp, i32, ctypes.c_float, vp, vp, i64, vp, i32, vp, i64,
+                                      vp, vp]
+    lib.fv_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.fv_batch_update_learned_2d.argtypes = [vp, i64, vp, vp, i64, vp, i64, f64, vp, vp, f64,
+                                               vp, vp]
+    for name in ("fv_learned_flux_accumulate", "fv_learned_coarse_grain",
+                 "fv_learned_face_samples", "fv_mlp_fit_normalization", "fv_mlp_workspace_words",
+                 "fv_mlp_train_step", "fv_mlp_forward", "fv_batch_update_learned_2d"):
+        getattr(lib, name).restype = i32
     lib.fv_cfl_timestep.argtypes = [vp, i64, vp, i32, f64, vp, vp, vp]
     lib.fv_cfl_timestep.restype = i32
     lib.fv_fill_halo.argtypes = [vp, i64, vp, vp, i64, i32, i32, i32, i32, i32, vp]
@@ -319,6 +334,131 @@ def fill_halo(patches, neighbours, q, *, dim, p, which=FV_OFFSETS_IN, stream=Non
     _dev_nbr(neighbours, n, dim)
     _check(library().fv_fill_halo(_ptr(patches), n, _ptr(neighbours), _ptr(q), q.numel(), which,
                                   dim, p, 1, dim + 2, _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Learned face-flux correction (2-D)
+# ---------------------------------------------------------------------------
+MLP_BLOB_WORDS = 5548
+MLP_TRAINED_WORDS = 5508  # W1 .. b3
+BLOB_OFFSETS = {"x_mean": 0, "x_scale": 16, "w1": 32, "b1": 1056, "w2": 1120, "b2": 5216,
+                "w3": 5280, "b3": 5536, "y_scale": 5540, "y_mean": 5544}
+
+
+def _dev_f32(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 device tensor")
+    return t
+
+
+def learned_flux_accumulate(q_fine, acc_x, acc_y, *, npx, npy, p=16, r=4, bc=0, weight=0.25,
+                            gamma=1.4, stream=None):
+    """fv_learned_flux_accumulate (see include/fv.h)."""
+    _dev_f64(q_fine, "q_fine")
+    _dev_f64(acc_x, "acc_x")
+    _dev_f64(acc_y, "acc_y")
+    ncx, ncy = npx * p // r, npy * p // r
+    if acc_x.numel() != 4 * ncy * (ncx + 1) or acc_y.numel() != 4 * (ncy + 1) * ncx:
+        raise ValueError("accumulator sizes do not match the coarse grid")
+    if q_fine.numel() < npx * npy * 4 * p * p:
+        raise ValueError("q_fine is smaller than the patch grid")
+    _check(library().fv_learned_flux_accumulate(_ptr(q_fine), npx, npy, p, r, bc, float(gamma),
+                                                float(weight), _ptr(acc_x), _ptr(acc_y),
+                                                _stream(stream)))
+
+
+def learned_coarse_grain(q_fine, q_coarse, *, npx, npy, p=16, r=4, stream=None):
+    _dev_f64(q_fine, "q_fine")
+    _dev_f64(q_coarse, "q_coarse")
+    if q_fine.numel() < npx * npy * 4 * p * p or \
+            q_coarse.numel() < (npx // r) * (npy // r) * 4 * p * p:
+        raise ValueError("buffers smaller than the patch grids")
+    _check(library().fv_learned_coarse_grain(_ptr(q_fine), npx, npy, p, r, _ptr(q_coarse),
+                                             _stream(stream)))
+
+
+def learned_face_samples(q_coarse, acc_x, acc_y, features, targets, indicator, *, npx, npy,
+                         p=16, bc=0, gamma=1.4, stream=None):
+    _dev_f64(q_coarse, "q_coarse")
+    _dev_f64(acc_x, "acc_x")
+    _dev_f64(acc_y, "acc_y")
+    if acc_x.numel() != 4 * npy * p * (npx * p + 1) or acc_y.numel() != 4 * (npy * p + 1) * npx * p:
+        raise ValueError("accumulator sizes do not match the grid")
+    for t, name in ((features, "features"), (targets, "targets"), (indicator, "indicator")):
+        _dev_f32(t, name)
+    nx, ny = npx * p, npy * p
+    nfaces = ny * (nx + 1) + (ny + 1) * nx
+    if features.numel() < 16 * nfaces or targets.numel() < 4 * nfaces or \
+            indicator.numel() < nfaces or q_coarse.numel() < npx * npy * 4 * p * p:
+        raise ValueError("sample buffers too small")
+    _check(library().fv_learned_face_samples(_ptr(q_coarse), npx, npy, p, bc, float(gamma),
+                                             _ptr(acc_x), _ptr(acc_y), _ptr(features),
+                                             _ptr(targets), _ptr(indicator), _stream(stream)))
+
+
+def mlp_fit_normalization(x, cols, mean_out, scale_out, *, mode, rows=None, stream=None):
+    _dev_f32(x, "x")
+    x_rows = x.numel() // cols
+    n = 0 if rows is None else rows.numel()
+    _check(library().fv_mlp_fit_normalization(_ptr(x), x_rows, cols, mode, _ptr(rows), n,
+                                              _ptr(mean_out), _ptr(scale_out), _stream(stream)))
+
+
+def mlp_workspace_words(batch):
+    return int(library().fv_mlp_workspace_words(batch))
+
+
+def mlp_train_step(blob, adam, step, lr, features, targets, batch_idx, workspace, grad_out=None,
+                   stream=None):
+    _dev_f32(blob, "blob")
+    _dev_f32(adam, "adam")
+    _dev_f32(workspace, "workspace")
+    if blob.numel() != MLP_BLOB_WORDS or adam.numel() < 2 * MLP_TRAINED_WORDS:
+        raise ValueError("blob or adam state has the wrong size")
+    if grad_out is not None and (_dev_f32(grad_out, "grad_out").numel() < MLP_TRAINED_WORDS):
+        raise ValueError(f"grad_out needs {MLP_TRAINED_WORDS} words")
+    _dev_f32(features, "features")
+    _dev_f32(targets, "targets")
+    n_rows = features.numel() // 16
+    if targets.numel() < 4 * n_rows:
+        raise ValueError("targets need 4 values per feature row")
+    _check(library().fv_mlp_train_step(_ptr(blob), _ptr(adam), int(step), float(lr),
+                                       _ptr(features), _ptr(targets), n_rows, _ptr(batch_idx),
+                                       batch_idx.numel(), _ptr(workspace), workspace.numel(),
+                                       _ptr(grad_out), _stream(stream)))
+
+
+def mlp_forward(blob, features, out, stream=None):
+    _dev_f32(blob, "blob")
+    _dev_f32(features, "features")
+    _dev_f32(out, "out")
+    n = features.numel() // 16
+    if out.numel() < 4 * n:
+        raise ValueError("out needs 4 values per row")
+    _check(library().fv_mlp_forward(_ptr(blob), _ptr(features), n, _ptr(out), _stream(stream)))
+
+
+def batch_update_learned_2d(patches, neighbours, q_in, q_out, blob, *, gamma=1.4, dt=None,
+                            threshold=0.2, max_eig=None, stream=None):
+    """fv_batch_update_learned_2d: 16^2 patches, compact blocks, corrected fluxes."""
+    _dev_f64(q_in, "q_in")
+    _dev_f64(q_out, "q_out")
+    _dev_f32(blob, "blob")
+    if dt is not None:
+        _dev_f64(dt, "dt")
+    if max_eig is not None:
+        _dev_f64(max_eig, "max_eig")
+    n = _n_patches(patches)
+    _dev_nbr(neighbours, n, 2)
+    if blob.numel() != MLP_BLOB_WORDS:
+        raise ValueError("blob has the wrong size")
+    _check(library().fv_batch_update_learned_2d(_ptr(patches), n, _ptr(neighbours), _ptr(q_in),
+                                                q_in.numel(), _ptr(q_out), q_out.numel(),
+                                                float(gamma), _ptr(dt), _ptr(blob),
+                                                float(threshold), _ptr(max_eig),
+                                                _stream(stream)))
 
 
 class Plan:

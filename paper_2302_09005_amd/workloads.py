@@ -487,3 +487,32 @@ def uneven_batch(n: int = 20000, seed: int = 0, sizes=UNEVEN_SIZES, ratio=UNEVEN
         for j, b in enumerate(idx):
             q[off[b]:off[b] + blk] = qc[j]
     return batch, q
+
+
+def grid_riemann_2d(patches_per_axis: int = 16, p: int = 16, seed: int = 0,
+                    rho=(0.1, 1.0), pres=(0.1, 1.0), vel=(-1.0, 1.0)
+                    ) -> Tuple[PatchGrid, np.ndarray]:
+    """Seeded 2-D four-quadrant Riemann problem on the unit square.
+
+    With rng = numpy.random.default_rng(seed): the split point (x0, y0) ~
+    U[0.3, 0.7]^2, then for the quadrants (x < x0, y < y0), (x >= x0, y < y0),
+    (x < x0, y >= y0), (x >= x0, y >= y0) in that order rho ~ U[rho], p ~
+    U[pres], u ~ U[vel], v ~ U[vel].  Transmissive boundaries on both axes.
+    """
+    n = patches_per_axis * p
+    grid = PatchGrid(2, p, (patches_per_axis, patches_per_axis), 1.0 / n,
+                     bc=(TRANSMISSIVE, TRANSMISSIVE))
+    x, y = grid.cell_centres()
+    rng = np.random.default_rng(seed)
+    x0, y0 = rng.uniform(0.3, 0.7, size=2)
+    states = []
+    for _ in range(4):
+        states.append((rng.uniform(*rho), rng.uniform(*pres), rng.uniform(*vel),
+                       rng.uniform(*vel)))
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    quad = (X >= x0).astype(int) + 2 * (Y >= y0).astype(int)
+    r = np.choose(quad, [s[0] for s in states])
+    pr = np.choose(quad, [s[1] for s in states])
+    u = np.choose(quad, [s[2] for s in states])
+    v = np.choose(quad, [s[3] for s in states])
+    return grid, to_conserved(r, [u, v], pr)

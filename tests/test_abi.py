@@ -219,3 +219,44 @@ def test_step_local_rejects_bad_arguments_on_host():
     assert lib.fv_local_timestep(0x1000, 4, None, 3, 0.4, None) == fv.FV_EINVAL
     assert lib.fv_local_timestep(0x1000, 4, 0x2000, 3, -0.4, None) == fv.FV_EINVAL
     assert lib.fv_local_timestep(0x1000, 0, None, 3, 0.4, None) == fv.FV_OK
+
+
+def test_learned_entry_points_reject_bad_arguments_on_host():
+    lib = fv.library()
+    # r must divide p; bc in {0, 1}; null pointers
+    assert lib.fv_learned_flux_accumulate(0x1000, 4, 4, 16, 3, 0, 1.4, 0.25, 0x2000, 0x3000,
+                                          None) == fv.FV_EINVAL
+    assert lib.fv_learned_flux_accumulate(0x1000, 4, 4, 16, 4, 2, 1.4, 0.25, 0x2000, 0x3000,
+                                          None) == fv.FV_EINVAL
+    assert lib.fv_learned_flux_accumulate(None, 4, 4, 16, 4, 0, 1.4, 0.25, 0x2000, 0x3000,
+                                          None) == fv.FV_EINVAL
+    assert lib.fv_learned_coarse_grain(0x1000, 6, 4, 16, 4, 0x2000, None) == fv.FV_EINVAL
+    assert lib.fv_learned_coarse_grain(0x1000, 4, 4, 16, 4, 0x1000, None) == fv.FV_EINVAL
+    assert lib.fv_mlp_fit_normalization(0x1000, 10, 16, 2, None, 0, 0x2000, 0x3000,
+                                        None) == fv.FV_EINVAL
+    assert lib.fv_mlp_train_step(0x1000, 0x2000, 0, 1e-3, 0x3000, 0x4000, 100, 0x5000, 64,
+                                 0x6000, 10 ** 6, None, None) == fv.FV_EINVAL  # step 0
+    assert lib.fv_mlp_train_step(0x1000, 0x2000, 1, 1e-3, 0x3000, 0x4000, 100, 0x5000, 64,
+                                 0x6000, 10, None, None) == fv.FV_EINVAL      # workspace
+    assert "workspace" in lib.fv_last_error().decode()
+    assert lib.fv_mlp_forward(0x1000, 0x2000, 0, 0x3000, None) == fv.FV_OK
+    assert lib.fv_batch_update_learned_2d(0x1000, 4, 0x2000, 0x3000, 100, 0x3000 + 8, 100, 1.4,
+                                          None, 0x4000, 0.2, None, None) == fv.FV_EINVAL
+    assert lib.fv_batch_update_learned_2d(0x1000, 4, 0x2000, 0x3000, 100, 0x8000, 100, 1.4,
+                                          None, 0x4000, -1.0, None, None) == fv.FV_EINVAL
+    assert fv.mlp_workspace_words(1024) == 1024 * 277
+
+
+def test_mlp_sizes_match_header_and_layout():
+    from oracle import learned as OL
+    src = open(os.path.join(ROOT, "include", "fv.h")).read()
+    blob = int(re.search(r"#define FV_MLP_BLOB_WORDS (\d+)", src).group(1))
+    trained = int(re.search(r"#define FV_MLP_TRAINED_WORDS (\d+)", src).group(1))
+    sizes = {name: int(np.prod(shape)) for name, shape in OL.BLOB_LAYOUT}
+    assert blob == fv.MLP_BLOB_WORDS == OL.BLOB_SIZE
+    assert trained == fv.MLP_TRAINED_WORDS == sum(sizes[k] for k in ("w1", "b1", "w2", "b2",
+                                                                    "w3", "b3"))
+    o = 0
+    for name, _ in OL.BLOB_LAYOUT:
+        assert fv.BLOB_OFFSETS[name] == o
+        o += sizes[name]
