@@ -7,6 +7,7 @@
 // 16 x 16 volumes and its two-volume face halo in LDS, evaluates all 544
 // faces (Rusanov flux in float64 plus the correction), then updates every
 // volume from its four face fluxes.
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "fv_euler.hpp"
@@ -351,9 +352,10 @@ int launch_update_learned_2d(const fv_patch* patches, int64_t n, const int64_t* 
                              double gamma, const double* dt_dev, const float* blob,
                              double threshold, double* max_eig, hipStream_t st) {
   if (n == 0) return 0;
-  hipLaunchKernelGGL(learned_update_kernel, dim3((unsigned)n), dim3(kThreads), 0, st, patches, n,
-                     neighbours, qin, qin_len, qout, qout_len, gamma, dt_dev, blob, threshold,
-                     max_eig);
+  const LaunchEvents& ev = launch_events();
+  hipExtLaunchKernelGGL(learned_update_kernel, dim3((unsigned)n), dim3(kThreads), 0, st, ev.start,
+                        ev.stop, 0, patches, n, neighbours, qin, qin_len, qout, qout_len, gamma,
+                        dt_dev, blob, threshold, max_eig);
   return 0;
 }
 
