@@ -32,6 +32,15 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
   return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
+// tanh(x) = 1 - 2 / (exp(2x) + 1) from the hardware base-2 exponential and
+// reciprocal (a few ulp of float32 away from the correctly rounded value;
+// the result is rounded to bfloat16 next, 2^-9 relative).  +-inf and large
+// |x| give +-1, NaN stays NaN.
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 / ln 2
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
 // Matrix-core lane layout of the 32 x 32 x 16 product (wave64): lane l holds
 // A[l % 32][8 (l / 32) + e] and B[8 (l / 32) + e][l % 32] for e = 0..7, and
 // accumulator register r holds C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
@@ -102,7 +111,7 @@ __device__ void mlp64(const MlpFrags& F, MlpLds& s, int l, const float (&xh)[kNF
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[rt], F.w1[ct], c, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        s.h[(32 * rt + acc_row(l, r)) * kNH + 32 * ct + j] = bf16_bits(tanhf(c[r] + F.b1[ct]));
+        s.h[(32 * rt + acc_row(l, r)) * kNH + 32 * ct + j] = bf16_bits(tanh_fast(c[r] + F.b1[ct]));
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -126,7 +135,7 @@ __device__ void mlp64(const MlpFrags& F, MlpLds& s, int l, const float (&xh)[kNF
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[rt][ks], F.w2[ct][ks], c, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        s.h[(32 * rt + acc_row(l, r)) * kNH + 32 * ct + j] = bf16_bits(tanhf(c[r] + F.b2[ct]));
+        s.h[(32 * rt + acc_row(l, r)) * kNH + 32 * ct + j] = bf16_bits(tanh_fast(c[r] + F.b2[ct]));
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -178,7 +187,8 @@ mlp_forward_kernel(const float* __restrict__ blob, const float* __restrict__ fea
 constexpr int kP = 16, kH = 2, kW = kP + 2 * kH;  // volumes per axis with the halo
 constexpr int kNXF = (kP + 1) * kP;              // x faces (= y faces) per patch
 constexpr int kNFACE = 2 * kNXF;                 // 544
-constexpr int kThreads = 256;
+constexpr int kVolThreads = kP * kP;  // one thread per volume in the update
+constexpr int kThreads = 512;         // eight waves share the 9 face batches
 
 struct PatchLds {
   double q[4][kW][kW];        // state with a two-volume face halo (corners unused)
@@ -223,7 +233,7 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   const double rx = dt / pd.dx[0], ry = dt / pd.dx[1];
 
   // ---- state and face halo into LDS --------------------------------------
-  {
+  if (tid < kVolThreads) {
     const int x = tid & 15, y = tid >> 4;
 #pragma unroll
     for (int m = 0; m < 4; ++m) s.q[m][y + kH][x + kH] = qin[pd.q_in + m * kP * kP + y * kP + x];
@@ -255,7 +265,7 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   }
   __syncthreads();
 
-  // ---- faces: 9 batches of 64 over the 4 waves ---------------------------
+  // ---- faces: 9 batches of 64 over the 8 waves ---------------------------
   const MlpFrags F = load_frags(blob, l);
   for (int batch = wave; batch * 64 < kNFACE; batch += kThreads / 64) {
     const int f = batch * 64 + l;
@@ -314,17 +324,20 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   __syncthreads();
 
   // ---- update, new-state maximum ----------------------------------------
-  const int x = tid & 15, y = tid >> 4;
-  double qn[4];
+  double lam = 0.0;  // threads past the volumes contribute nothing
+  if (tid < kVolThreads) {
+    const int x = tid & 15, y = tid >> 4;
+    double qn[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    double v = s.q[m][y + kH][x + kH] - rx * (s.fx[m][y][x + 1] - s.fx[m][y][x]);
-    v = v - ry * (s.fy[m][y + 1][x] - s.fy[m][y][x]);
-    qn[m] = v;
-    qout[pd.q_out + m * kP * kP + y * kP + x] = v;
+    for (int m = 0; m < 4; ++m) {
+      double v = s.q[m][y + kH][x + kH] - rx * (s.fx[m][y][x + 1] - s.fx[m][y][x]);
+      v = v - ry * (s.fy[m][y + 1][x] - s.fy[m][y][x]);
+      qn[m] = v;
+      qout[pd.q_out + m * kP * kP + y * kP + x] = v;
+    }
+    const Prim<double> wn = decode<double, 2>(qn, gamma);
+    lam = max_wave_speed<double, 2>(qn, wn);
   }
-  const Prim<double> wn = decode<double, 2>(qn, gamma);
-  double lam = max_wave_speed<double, 2>(qn, wn);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) lam = nanmax_pos(lam, __shfl_xor(lam, o, 64));
   if (l == 0) s.red[wave] = lam;
