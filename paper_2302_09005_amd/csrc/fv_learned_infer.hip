@@ -285,7 +285,6 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
 #pragma unroll
       for (int m = 0; m < 4; ++m) v[o][m] = s.q[m][cy][cx];
     }
-    const int tn = xdir ? 1 : 2, tt = xdir ? 2 : 1;
     float xh[kNF];
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
@@ -310,8 +309,6 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
 #pragma unroll
     for (int c = 0; c < 4; ++c) dfr[c] = corr ? (double)(out[c] * blob[kYS + c] + blob[kYM + c]) : 0.0;
     const double dF[4] = {dfr[0], xdir ? dfr[1] : dfr[2], xdir ? dfr[2] : dfr[1], dfr[3]};
-    (void)tn;
-    (void)tt;
     if (real) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {

@@ -46,8 +46,9 @@ class PatchRun:
 
     def cfl_dt(self, cfl):
         """dt = cfl * dx / (2 Lambda) of the current state, on the device."""
+        import torch
         fv.max_eigenvalue(self.patches, self.a, self.per, dim=2, p=P, q_halo=False)
-        out = torch_empty_like(self.dt)
+        out = torch.empty_like(self.dt)
         fv.cfl_timestep(self.patches, self.per, dim=2, cfl=cfl, dt_out=out)
         return out
 
@@ -62,11 +63,6 @@ class PatchRun:
 
     def global_state(self):
         return self.grid.unpack(self.a.cpu().numpy(), halo=False)
-
-
-def torch_empty_like(t):
-    import torch
-    return torch.empty_like(t)
 
 
 def fine_run(seed, coarse_steps, device="cuda", collect=True, threshold=THRESHOLD):
@@ -162,7 +158,6 @@ def evaluate(blob, seed, coarse_steps, device="cuda", threshold=THRESHOLD):
     """Coarse plain and learned runs of a held-out Riemann problem against the
     coarse-grained fine run, with the fine run's coarse steps.  Returns L1
     errors per unknown (mean over volumes) after every coarse step."""
-    import torch
     _, truth, dts = fine_run(seed, coarse_steps, device, collect=False)
     grid, _ = W.grid_riemann_2d(COARSE, P, seed)
     q0 = grid.unpack(truth[0].cpu().numpy(), halo=False)

@@ -260,3 +260,12 @@ def test_mlp_sizes_match_header_and_layout():
     for name, _ in OL.BLOB_LAYOUT:
         assert fv.BLOB_OFFSETS[name] == o
         o += sizes[name]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

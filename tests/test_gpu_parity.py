@@ -566,3 +566,44 @@ def test_ragged_batch_sizes(n):
     assert np.abs(got[m] - ref[m]).max() <= TOL * np.abs(ref[m]).max()
     assert ((got == -123.0) == (ref == -123.0)).all()
     np.testing.assert_allclose(me, me_ref, rtol=LAM_TOL)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_fused_steps_in_a_graph_match_eager_bitwise(dtype):
+    """The fused step captured as a HIP graph (how the benchmark times it),
+    replayed three times with other eager work and synchronisations between
+    replays, gives the eager steps' state, time step and maxima bit for bit
+    after every replay, and leaves the workspace zeroed."""
+    import torch
+    grid, q = W.grid_3d_random_smooth(8, 8, seed=31)
+    desc = grid.descriptors(out_halo=False, in_halo=False)
+    mk = lambda: fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=3, p=8,
+                            mode="fused", dtype=dtype)
+    g_st, e_st = mk(), mk()
+    for st in (g_st, e_st):          # a few eager steps first, as the benchmark does
+        for _ in range(3):
+            st.step()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(6):
+                g_st.update()
+                g_st.swap()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    x = torch.randn(1 << 16, device="cuda", dtype=torch.float64)
+    for rep in range(3):
+        graph.replay()
+        for _ in range(6):
+            e_st.update()
+            e_st.swap()
+        y = float((x * x).sum().item())
+        torch.cuda.synchronize()
+        _say(f"[fused graph replay {rep}, {np.dtype(dtype).name}] {y:.3f}")
+        assert torch.equal(g_st.state(), e_st.state())
+        assert torch.equal(g_st.last_dt(), e_st.last_dt())
+        assert torch.equal(g_st.per_patch, e_st.per_patch)
+        assert (g_st.workspace.cpu().numpy() == 0).all()
