@@ -1,8 +1,8 @@
 """Pins of the learned-correction oracle (oracle/learned.py) against things
-other than itself: the C oracle's plain update, torch's bfloat16 rounding,
-closed forms (uniform states, constant corrections, exact averages), the
-telescoping identity between fine and coarse updates, and finite
-differences of the loss."""
+other than itself: the C oracle's plain update, torch's bfloat16 rounding
+and Linear/Tanh layers with autograd, closed forms (uniform states, constant
+corrections, exact averages), the telescoping identity between fine and
+coarse updates, and finite differences of the loss."""
 import math
 
 import numpy as np
@@ -206,3 +206,43 @@ def test_blob_layout_round_trip():
     q = L.unpack_blob(blob)
     for k in p:
         np.testing.assert_array_equal(q[k], p[k])
+
+
+def _torch_mlp(params, dtype):
+    import torch
+    net = torch.nn.Sequential(torch.nn.Linear(16, 64), torch.nn.Tanh(), torch.nn.Linear(64, 64),
+                              torch.nn.Tanh(), torch.nn.Linear(64, 4)).to(dtype)
+    with torch.no_grad():
+        for layer, (w, b) in zip((net[0], net[2], net[4]), (("w1", "b1"), ("w2", "b2"), ("w3", "b3"))):
+            layer.weight.copy_(torch.from_numpy(np.asarray(params[w], np.float64)))
+            layer.bias.copy_(torch.from_numpy(np.asarray(params[b], np.float64)))
+    return net
+
+
+def test_network_definition_against_torch_layers():
+    """The oracle's network is torch's Linear-Tanh-Linear-Tanh-Linear with
+    weights stored [out][in]: the float64 loss and its gradients match torch
+    autograd, and the bfloat16-operand forward stays within bfloat16 rounding
+    of the float64 one (a transposed square W2 would not)."""
+    import torch
+    rng = np.random.default_rng(21)
+    p = {k: v.astype(np.float64) for k, v in _random_params(22, scale=0.4).items()}
+    x = rng.standard_normal((50, 16))
+    y = rng.standard_normal((50, 4))
+    loss, g = L.mlp_loss_grads(x, y, p)
+    net = _torch_mlp(p, torch.float64)
+    out = net(torch.from_numpy(x))
+    tl = torch.mean((out - torch.from_numpy(y)) ** 2)
+    tl.backward()
+    assert abs(tl.item() - loss) <= 1e-14 * loss
+    for layer, (w, b) in zip((net[0], net[2], net[4]), (("w1", "b1"), ("w2", "b2"), ("w3", "b3"))):
+        np.testing.assert_allclose(g[w], layer.weight.grad.numpy(), rtol=1e-11, atol=1e-14)
+        np.testing.assert_allclose(g[b], layer.bias.grad.numpy(), rtol=1e-11, atol=1e-14)
+    p32 = {k: v.astype(np.float32) for k, v in p.items()}
+    o_bf = L.mlp_forward(x.astype(np.float32), p32)
+    with torch.no_grad():
+        o64 = net(torch.from_numpy(x)).numpy()
+    assert np.abs(o_bf - o64).max() <= 0.05 * np.abs(o64).max()
+    pt = dict(p32)
+    pt["w2"] = p32["w2"].T.copy()
+    assert np.abs(L.mlp_forward(x.astype(np.float32), pt) - o64).max() > 0.1 * np.abs(o64).max()
