@@ -11,16 +11,20 @@ step of the next step.  Inputs are resident in HBM before the timed region
 starts.  The paper's interface (halo'd blocks, update, separate halo fill) is
 timed afterwards and reported under detail.plain_halo_path.
 
-The timed steps run as one HIP graph (captured once, replayed once untimed and
-once timed with events on the stream that runs it), so consecutive steps are
-not separated by host launch gaps.
+The timed steps run as one HIP graph (captured once, replayed untimed for
+--ramp-s seconds of wall time, then once timed with events on the stream that
+runs it), so consecutive steps are not separated by host launch gaps.  The
+untimed replays bring the GPU to its sustained clock: a timed region that
+starts right after an idle period measures the clock ramp (about 20 % slower
+over the first tens of milliseconds), not the steady state.
 
 Prints ONE JSON line: cell-updates/s over the timed steps, the roofline of the
 dominant kernel (the update; algorithmic bytes / its average duration, the
 timed replay divided by the steps) and the CPU oracle timed on a bounded sample
 of the same workload.
 
-    python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--ramp-s 0.3]
+                    [--no-cpu-baseline]
 """
 import argparse
 import hashlib
@@ -173,12 +177,50 @@ def plain_path(grid, q, steps):
             "update_hbm_frac": bpc * grid.cells / (upd_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
-def fp32_path(grid, q, steps, warmup, ref_state):
-    """The same fused step with FP32 state (FP64 maxima / CFL), run exactly as
-    the FP64 line (eager warm-up, a graph of the timed steps replayed twice,
-    20 eager steps): throughput, kernel time, roofline at the FP32
-    algorithmic bytes, and the relative difference to the FP64 state after
-    the same steps."""
+def ramp(graph, seconds):
+    """Replay a captured graph, untimed, until `seconds` of wall time have
+    passed (at least once), so that the timed replay runs at the sustained
+    clock.  Returns the number of replays."""
+    import torch
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        graph.replay()
+        torch.cuda.synchronize()
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            return n
+
+
+def fp32_vs_fp64(grid, q, steps):
+    """Relative L2 and Linf differences (worst unknown) between the FP32 and
+    the FP64 fused steps after the same number of eager steps from the same
+    initial state."""
+    import torch
+    from paper_2302_09005_amd import fv
+    out = {}
+    for name, dt in (("f64", np.float64), ("f32", np.float32)):
+        st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
+                        grid.pack_compact(q), dim=grid.d, p=grid.p, mode="fused", dtype=dt)
+        for _ in range(steps):
+            st.step()
+        torch.cuda.synchronize()
+        out[name] = st.state().double()
+        del st
+    a, r = out["f32"], out["f64"]
+    s = grid.s
+    d = (a - r).view(s, -1)
+    rv = r.view(s, -1)
+    return (float((d.norm(dim=1) / rv.norm(dim=1)).max()),
+            float((d.abs().amax(dim=1) / rv.abs().amax(dim=1)).max()))
+
+
+def fp32_path(grid, q, steps, warmup, ramp_s, cmp_steps=100):
+    """The same fused step with FP32 state (FP64 maxima / CFL), timed exactly
+    as the FP64 line (eager warm-up, a graph of the timed steps, untimed
+    replays for ramp_s seconds, one timed replay): throughput, kernel time,
+    roofline at the FP32 algorithmic bytes; and the relative difference to
+    the FP64 state after cmp_steps steps from the same initial state."""
     import torch
     from paper_2302_09005_amd import fv
     st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
@@ -195,37 +237,26 @@ def fp32_path(grid, q, steps, warmup, ref_state):
                 st.update()
                 st.swap()
     stream.wait_stream(side)
-    graph.replay()
-    torch.cuda.synchronize()
+    ramp(graph, ramp_s)
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record(stream)
     graph.replay()
     t1.record(stream)
     torch.cuda.synchronize()
     total = t0.elapsed_time(t1)
-    del graph
-    for _ in range(20):
-        st.update()
-        st.swap()
-    torch.cuda.synchronize()
-    a = st.state().double()
-    r = ref_state
-    s = grid.s
-    d = (a - r).view(s, -1)
-    rv = r.view(s, -1)
-    l2 = float((d.norm(dim=1) / rv.norm(dim=1)).max())
-    li = float((d.abs().amax(dim=1) / rv.abs().amax(dim=1)).max())
+    del graph, st
+    l2, li = fp32_vs_fp64(grid, q, cmp_steps)
     bpc = algorithmic_bytes_per_cell(grid.d, grid.p, grid.s, 4)
     upd_us = total * 1e3 / steps
     return {"steps": steps, "cell_updates_per_s": grid.cells * steps / (total * 1e-3),
             "ms_per_step": total / steps, "update_us": upd_us,
             "algorithmic_bytes_per_cell": bpc,
             "update_hbm_frac": bpc * grid.cells / (upd_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-            "rel_l2_vs_fp64": l2, "rel_linf_vs_fp64": li,
+            "rel_l2_vs_fp64": l2, "rel_linf_vs_fp64": li, "compared_after_steps": cmp_steps,
             "speedup_vs_fp64_step": None}
 
 
-def uneven_path(seed, steps=50, dtype=None, tune=True, schedule=("persistent", 0)):
+def uneven_path(seed, steps=50, dtype=None, tune=True, schedule=("persistent", 0), ramp_s=0.3):
     """The uneven AMR-like batch: 20 000 self-periodic 3-D patches of 4^3, 8^3
     and 16^3 volumes (4:2:1), levels 2-4 (dx = 3^-l / p), local time steps.
     The schedule is picked by the autotuner (per size class, persistent
@@ -267,8 +298,7 @@ def uneven_path(seed, steps=50, dtype=None, tune=True, schedule=("persistent", 0
             for _ in range(n_cap):
                 st.step()
     torch.cuda.current_stream().wait_stream(side)
-    graph.replay()  # warm
-    torch.cuda.synchronize()
+    ramp(graph, ramp_s)
     reps = 3
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     ev[0].record()
@@ -487,8 +517,10 @@ def copy_calibration(mib=1024, reps=5):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--ramp-s", type=float, default=0.3,
+                    help="untimed graph replays before each timed replay (seconds)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true",
@@ -537,8 +569,8 @@ def main():
 
     # The timed region: the K steps captured once as a HIP graph (one fused
     # kernel node per step, so the steps run back to back without host
-    # launch gaps), replayed once untimed and once timed with events on the
-    # stream that runs it.  The per-launch kernel time is the timed replay
+    # launch gaps), replayed untimed for ramp_s seconds (sustained clock)
+    # and once timed with events on the stream that runs it.  The per-launch kernel time is the timed replay
     # divided by K (an upper bound: it includes the gap between graph nodes).
     stream = torch.cuda.current_stream()
     graph = torch.cuda.CUDAGraph()
@@ -550,8 +582,7 @@ def main():
                 st.update()
                 st.swap()
     stream.wait_stream(side)
-    graph.replay()
-    torch.cuda.synchronize()
+    ramp_replays = ramp(graph, args.ramp_s)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     t_start.record(stream)
@@ -585,7 +616,7 @@ def main():
     # the paper's interface for comparison: halo'd blocks, update + separate halo fill
     plain = plain_path(grid, q, min(args.steps, 20))
     # FP32 bulk arithmetic on the same workload and step count
-    f32 = fp32_path(grid, q, args.steps, args.warmup, state)
+    f32 = fp32_path(grid, q, args.steps, args.warmup, args.ramp_s)
     f32["speedup_vs_fp64_step"] = (total_ms / args.steps) / f32["ms_per_step"]
 
     # uneven AMR-like batch with local time steps (FP64, then FP32 bulk)
@@ -594,12 +625,12 @@ def main():
         sched, wg = args.uneven_schedule.split(":")
         fixed = (sched, int(wg))
     uneven = None if args.no_uneven else (
-        uneven_path(args.seed) if fixed is None else
-        uneven_path(args.seed, tune=False, schedule=fixed))
+        uneven_path(args.seed, ramp_s=args.ramp_s) if fixed is None else
+        uneven_path(args.seed, tune=False, schedule=fixed, ramp_s=args.ramp_s))
     uneven32 = None
     if uneven is not None:
         uneven32 = uneven_path(args.seed, dtype=np.float32, tune=False,
-                               schedule=tuple(uneven["schedule"]["chosen"]))
+                               schedule=tuple(uneven["schedule"]["chosen"]), ramp_s=args.ramp_s)
 
     learned_detail = None if args.no_learned else learned_path(args.seed)
 
@@ -632,7 +663,9 @@ def main():
                      "algorithmic_bytes_per_cell": bpc,
                      "kernel_avg_us": upd_ms.mean() * 1e3},
         "detail": {"update_cell_updates_per_s": cells / upd_s,
-                   "timing": "HIP graph of the timed steps; kernel_avg_us = replay time / steps",
+                   "timing": "HIP graph of the timed steps, replayed untimed for ramp_s seconds "
+                             "first; kernel_avg_us = timed replay time / steps",
+                   "ramp_s": args.ramp_s, "ramp_replays": ramp_replays,
                    "eager_dispatch_event_us": eager_dispatch_us,
                    "eager_step_us": eager_step_us,
                    "final_lambda": lam_final, "state_finite": finite,
