@@ -480,13 +480,32 @@ def learned_path(seed, train_seeds=(101, 102, 103), coarse_steps=8, epochs=20,
         hip.destroy()
         return us
 
-    for _ in range(3):
-        run.step_plain(dt)
-        run.step_learned(dt, blob)
+    def warm(r, dt_r):
+        t_w = _time.perf_counter()
+        while _time.perf_counter() - t_w < 0.2:
+            for _ in range(10):
+                r.step_plain(dt_r)
+                r.step_learned(dt_r, blob)
+            torch.cuda.synchronize()
+
+    warm(run, dt)
     plain_us = timed(lambda: run.step_plain(dt))
     learned_us = timed(lambda: run.step_learned(dt, blob))
-    faces = 2 * 17 * 16 * grid.n
-    flops = faces * 2 * (16 * 64 + 64 * 64 + 64 * 4)
+    flop_face = 2 * (16 * 64 + 64 * 64 + 64 * 4)
+    flops = 2 * 17 * 16 * grid.n * flop_face
+    # the same kernels on a 16x larger batch (64 x 64 patches of 16^2, its own
+    # CFL step): throughput once the launch fills the chip
+    big, qb = W.grid_riemann_2d(4 * learned.COARSE, learned.P, 200 + seed)
+    runb = learned.PatchRun(big, qb)
+    dtb = runb.cfl_dt(learned.CFL)
+    warm(runb, dtb)
+    plain_big = timed(lambda: runb.step_plain(dtb))
+    learned_big = timed(lambda: runb.step_learned(dtb, blob))
+    cells_big = big.n * learned.P ** 2
+    at_scale = {"patches": big.n, "plain_update_us": plain_big, "learned_update_us": learned_big,
+                "learned_cell_updates_per_s": cells_big / (learned_big * 1e-6),
+                "mlp_tflops": 2 * 17 * 16 * big.n * flop_face / (learned_big * 1e-6) / 1e12}
+    del runb
     last = {k: v[-1] for k, v in ev.items()}
     return {"workload": "2d-euler-256x16^2-riemann, 4x finer reference runs",
             "samples": int(n_all), "samples_used": int(f.shape[0]),
@@ -498,7 +517,31 @@ def learned_path(seed, train_seeds=(101, 102, 103), coarse_steps=8, epochs=20,
             "l1_rho_per_step": {"plain": [e[0] for e in ev["plain"]],
                                 "learned": [e[0] for e in ev["learned"]]},
             "plain_update_us": plain_us, "learned_update_us": learned_us,
-            "mlp_tflops": flops / (learned_us * 1e-6) / 1e12}
+            "mlp_tflops": flops / (learned_us * 1e-6) / 1e12,
+            "at_scale": at_scale}
+
+
+def copy_bandwidth(mib=1024, reps=10):
+    """Bytes moved per second (read + write) by a plain 1 GiB device-to-device
+    copy, median of `reps` after 0.2 s of untimed copies: the HBM rate a
+    streaming kernel can reach on this machine, beside the 8 TB/s published peak."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.2:
+        dst.copy_(src)
+        torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for r in range(reps):
+        dst.copy_(src)
+        ev[r + 1].record()
+    torch.cuda.synchronize()
+    ms = float(np.median([ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]))
+    del src, dst
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
 def copy_calibration(mib=1024, reps=5):
@@ -633,6 +676,7 @@ def main():
                                schedule=tuple(uneven["schedule"]["chosen"]), ramp_s=args.ramp_s)
 
     learned_detail = None if args.no_learned else learned_path(args.seed)
+    copy_gbs = copy_bandwidth()
 
     cells = grid.cells
     value = cells * args.steps / (total_ms * 1e-3)
@@ -673,7 +717,10 @@ def main():
                    "fp32_path": f32,
                    "uneven_batch": uneven,
                    "uneven_batch_fp32": uneven32,
-                   "learned_flux": learned_detail},
+                   "learned_flux": learned_detail,
+                   "copy_bandwidth_gbs": copy_gbs,
+                   "update_algorithmic_over_copy": achieved / copy_gbs,
+                   "update_traffic_gbs": (traffic / upd_s / 1e9) if traffic else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid, grid.pack(q), args.cpu_budget, 100)

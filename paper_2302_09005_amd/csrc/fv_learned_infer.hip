@@ -1,12 +1,12 @@
 // Learned face-flux correction, 2-D Euler: inference.  The per-face network
 // (16 -> 64 -> 64 -> 4, tanh) runs on the matrix cores: one wave evaluates 64
-// faces at a time as three bfloat16 products with float32 sums
-// (v_mfma_f32_32x32x16_bf16: a 32 x 16 by 16 x 32 product per instruction;
-// layer 1 is 2 x 2 instructions, layer 2 2 x 2 x 4, layer 3 2 x 1 x 4 with
-// the four outputs padded to 32 columns).  The fused update keeps a patch of
-// 16 x 16 volumes and its two-volume face halo in LDS, evaluates all 544
-// faces (Rusanov flux in float64 plus the correction), then updates every
-// volume from its four face fluxes.
+// faces at a time, as two tiles of 32 faces, with three bfloat16 products per
+// tile and float32 sums (v_mfma_f32_32x32x16_bf16; layer 1 is 2
+// instructions per tile, layer 2 2 x 4, layer 3 4 with the four outputs
+// padded to 32 rows).  The fused update keeps a patch of 16 x 16 volumes and
+// its two-volume face halo in LDS, evaluates all 544 faces (Rusanov flux in
+// float64 plus the correction), then updates every volume from its four face
+// fluxes.
 #include <hip/hip_ext.h>
 #include <math.h>
 
@@ -25,11 +25,24 @@ constexpr int kXM = 0, kXS = 16, kW1 = 32, kB1 = kW1 + kNH * kNF, kW2 = kB1 + kN
               kB2 = kW2 + kNH * kNH, kW3 = kB2 + kNH, kB3 = kW3 + kNO * kNH, kYS = kB3 + kNO,
               kYM = kYS + kNO;
 
-// float32 -> bfloat16 bits, round to nearest even; NaN stays NaN.
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  const unsigned u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
-  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+// Two float32 values as a pair of bfloat16 (round to nearest even, the
+// hardware conversion; NaN stays NaN).
+__device__ __forceinline__ bf16x2 to_bf16x2(float a, float b) {
+  const floatx2 v = {a, b};
+  return __builtin_convertvector(v, bf16x2);
+}
+__device__ __forceinline__ bf16x8 to_bf16x8(const float* v) {
+  bf16x8 f;
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    const bf16x2 p = to_bf16x2(v[e], v[e + 1]);
+    f[e] = p[0];
+    f[e + 1] = p[1];
+  }
+  return f;
 }
 
 // tanh(x) = 1 - 2 / (exp(2x) + 1) from the hardware base-2 exponential and
@@ -41,123 +54,128 @@ __device__ __forceinline__ float tanh_fast(float x) {
   return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
 
-// Matrix-core lane layout of the 32 x 32 x 16 product (wave64): lane l holds
-// A[l % 32][8 (l / 32) + e] and B[8 (l / 32) + e][l % 32] for e = 0..7, and
-// accumulator register r holds C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-__device__ __forceinline__ int acc_row(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+// Matrix-core lane layout of the 32 x 32 x 16 product (wave64), lane
+// l = 32 h + j: the lane holds A[j][8 h + e] and B[8 h + e][j] for e = 0..7,
+// and accumulator register r holds C[8 (r / 4) + 4 h + r % 4][j].
+//
+// The network runs transposed, H^T = W X^T: units are rows, the 32 faces of a
+// tile are columns, so face j stays in lanes j and 32 + j throughout.  The
+// accumulator registers r = 8 q + e (e = 0..7) of the unit tile mt hold the
+// units 32 mt + 16 q + 8 (e / 4) + 4 h + e % 4 of face j, which is the B
+// operand of the next layer's k-step s = 2 mt + q once that layer's weight
+// columns are taken in the order unit_of(s, h, e).  So the hidden layers
+// never leave the registers.
+__device__ __forceinline__ int unit_of(int s, int h, int e) {
+  return 16 * s + 8 * (e >> 2) + 4 * h + (e & 3);
+}
 
 struct MlpFrags {
-  bf16x8 w1[2];      // [col tile]
-  bf16x8 w2[2][4];   // [col tile][k step]
-  bf16x8 w3[4];      // [k step], columns >= 4 zero
-  float b1[2], b2[2], b3;  // biases of this lane's columns
+  bf16x8 w1[2];      // [unit tile]: W1[32 mt + j][8 h + e]
+  bf16x8 w2[2][4];   // [unit tile][k step]: W2[32 mt + j][unit_of(s, h, e)]
+  bf16x8 w3[4];      // [k step]: W3[j][unit_of(s, h, e)], rows j >= 4 zero
 };
-
-__device__ __forceinline__ bf16x8 frag_from(const float* row, bool valid) {
-  bf16x8 f;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const unsigned short h = valid ? bf16_bits(row[e]) : (unsigned short)0;
-    f[e] = __builtin_bit_cast(__bf16, h);
-  }
-  return f;
-}
 
 __device__ MlpFrags load_frags(const float* __restrict__ blob, int l) {
   MlpFrags F;
-  const int j = l & 31, kh = 8 * (l >> 5);
+  const int j = l & 31, h = l >> 5;
+  float v[8];
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct) {
-    F.w1[ct] = frag_from(blob + kW1 + (32 * ct + j) * kNF + kh, true);
+  for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-      F.w2[ct][ks] = frag_from(blob + kW2 + (32 * ct + j) * kNH + 16 * ks + kh, true);
-    F.b1[ct] = blob[kB1 + 32 * ct + j];
-    F.b2[ct] = blob[kB2 + 32 * ct + j];
+    for (int e = 0; e < 8; ++e) v[e] = blob[kW1 + (32 * mt + j) * kNF + 8 * h + e];
+    F.w1[mt] = to_bf16x8(v);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = blob[kW2 + (32 * mt + j) * kNH + unit_of(ks, h, e)];
+      F.w2[mt][ks] = to_bf16x8(v);
+    }
   }
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks)
-    F.w3[ks] = frag_from(blob + kW3 + (j < kNO ? j : 0) * kNH + 16 * ks + kh, j < kNO);
-  F.b3 = j < kNO ? blob[kB3 + j] : 0.0f;
+  for (int ks = 0; ks < 4; ++ks) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = j < kNO ? blob[kW3 + j * kNH + unit_of(ks, h, e)] : 0.0f;
+    F.w3[ks] = to_bf16x8(v);
+  }
   return F;
 }
 
-// Per-wave LDS scratch of the network.
-struct MlpLds {
-  alignas(16) unsigned short x[64 * kNF];   // bfloat16 inputs [face][feature]
-  alignas(16) unsigned short h[64 * kNH];   // bfloat16 hidden layer [face][unit]
-  float o[64 * kNO];            // outputs [face][output]
+// Biases in accumulator order, [unit tile][h][register]: a layer starts its
+// sums from them.  One copy per workgroup, filled by fill_bias.
+struct MlpBias {
+  float b1[2][2][16];
+  float b2[2][2][16];
+  float b3[2][16];
 };
+
+__device__ void fill_bias(const float* __restrict__ blob, MlpBias& b, int tid, int nthreads) {
+  for (int i = tid; i < 64; i += nthreads) {
+    const int mt = i >> 5, h = (i >> 4) & 1, r = i & 15;
+    const int u = 32 * mt + 8 * (r >> 2) + 4 * h + (r & 3);
+    b.b1[mt][h][r] = blob[kB1 + u];
+    b.b2[mt][h][r] = blob[kB2 + u];
+    if (mt == 0) b.b3[h][r] = (h == 0 && r < kNO) ? blob[kB3 + r] : 0.0f;
+  }
+}
+
+// Per-wave LDS of the network: the bfloat16 features of the 64 faces (the
+// layer-1 operand of both tiles) and the 4 outputs of each face.
+struct MlpLds {
+  alignas(16) bf16x8 x[64][2];   // [face][feature / 8]
+  alignas(16) float o[64][kNO];  // [face][output]
+};
+
+// tanh of an accumulator tile, packed as the two k-step operands of the next
+// layer.
+__device__ __forceinline__ void tanh_pack(const floatx16& c, bf16x8& k0, bf16x8& k1) {
+  float t[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) t[r] = tanh_fast(c[r]);
+  k0 = to_bf16x8(t);
+  k1 = to_bf16x8(t + 8);
+}
 
 // The network on the 64 faces of this wave: lane l holds the normalised
 // features xh[16] of face l and receives its outputs o[4].  Wave-local: the
 // LDS traffic of one wave is ordered, so no workgroup barrier is needed.
-__device__ void mlp64(const MlpFrags& F, MlpLds& s, int l, const float (&xh)[kNF],
-                      float (&o)[kNO]) {
-  const int j = l & 31, kh = 8 * (l >> 5);
-#pragma unroll
-  for (int k = 0; k < kNF; ++k) s.x[l * kNF + k] = bf16_bits(xh[k]);
+__device__ void mlp64(const MlpFrags& F, const MlpBias& B, MlpLds& s, int l,
+                      const float (&xh)[kNF], float (&o)[kNO]) {
+  const int j = l & 31, h = l >> 5;
+  s.x[l][0] = to_bf16x8(xh);
+  s.x[l][1] = to_bf16x8(xh + 8);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // layer 1
-  bf16x8 a1[2];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt) a1[rt] = *reinterpret_cast<const bf16x8*>(&s.x[(32 * rt + j) * kNF + kh]);
+  for (int t = 0; t < 2; ++t) {
+    const bf16x8 xt = s.x[32 * t + j][h];  // X^T tile: features 8 h + e of face 32 t + j
+    bf16x8 h1[4], h2[4];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      floatx16 c = {};
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[rt], F.w1[ct], c, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        s.h[(32 * rt + acc_row(l, r)) * kNH + 32 * ct + j] = bf16_bits(tanh_fast(c[r] + F.b1[ct]));
+    for (int mt = 0; mt < 2; ++mt) {
+      floatx16 c = *reinterpret_cast<const floatx16*>(B.b1[mt][h]);
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.w1[mt], xt, c, 0, 0, 0);
+      tanh_pack(c, h1[2 * mt], h1[2 * mt + 1]);
     }
-  }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // layer 2 (all of h1 is read before h2 overwrites it)
-  bf16x8 a2[2][4];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-      a2[rt][ks] = *reinterpret_cast<const bf16x8*>(&s.h[(32 * rt + j) * kNH + 16 * ks + kh]);
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      floatx16 c = {};
+    for (int mt = 0; mt < 2; ++mt) {
+      floatx16 c = *reinterpret_cast<const floatx16*>(B.b2[mt][h]);
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
-        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[rt][ks], F.w2[ct][ks], c, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        s.h[(32 * rt + acc_row(l, r)) * kNH + 32 * ct + j] = bf16_bits(tanh_fast(c[r] + F.b2[ct]));
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.w2[mt][ks], h1[ks], c, 0, 0, 0);
+      tanh_pack(c, h2[2 * mt], h2[2 * mt + 1]);
     }
-  }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // layer 3
+    floatx16 c = *reinterpret_cast<const floatx16*>(B.b3[h]);
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-    floatx16 c = {};
+    for (int ks = 0; ks < 4; ++ks)
+      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.w3[ks], h2[ks], c, 0, 0, 0);
+    if (h == 0) {  // rows 0..3 = the outputs of face 32 t + j
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&s.h[(32 * rt + j) * kNH + 16 * ks + kh]);
-      c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, F.w3[ks], c, 0, 0, 0);
-    }
-    if (j < kNO) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) s.o[(32 * rt + acc_row(l, r)) * kNO + j] = c[r] + F.b3;
+      for (int m = 0; m < kNO; ++m) s.o[32 * t + j][m] = c[m];
     }
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-  for (int m = 0; m < kNO; ++m) o[m] = s.o[l * kNO + m];
+  for (int m = 0; m < kNO; ++m) o[m] = s.o[l][m];
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -167,14 +185,17 @@ __global__ void __launch_bounds__(64)
 mlp_forward_kernel(const float* __restrict__ blob, const float* __restrict__ feats, int64_t n,
                    float* __restrict__ out) {
   __shared__ MlpLds s;
+  __shared__ MlpBias bias;
   const int l = threadIdx.x;
   const int64_t row = (int64_t)blockIdx.x * 64 + l;
+  fill_bias(blob, bias, l, 64);
+  __syncthreads();
   const MlpFrags F = load_frags(blob, l);
   const int64_t rr = row < n ? row : n - 1;
   float xh[kNF], o[kNO];
 #pragma unroll
   for (int k = 0; k < kNF; ++k) xh[k] = (feats[rr * kNF + k] - blob[kXM + k]) * blob[kXS + k];
-  mlp64(F, s, l, xh, o);
+  mlp64(F, bias, s, l, xh, o);
   if (row < n) {
 #pragma unroll
     for (int m = 0; m < kNO; ++m) out[row * kNO + m] = o[m];
@@ -188,13 +209,14 @@ constexpr int kP = 16, kH = 2, kW = kP + 2 * kH;  // volumes per axis with the h
 constexpr int kNXF = (kP + 1) * kP;              // x faces (= y faces) per patch
 constexpr int kNFACE = 2 * kNXF;                 // 544
 constexpr int kVolThreads = kP * kP;  // one thread per volume in the update
-constexpr int kThreads = 512;         // eight waves share the 9 face batches
+constexpr int kThreads = 256;         // four waves share the 9 face batches
 
 struct PatchLds {
   double q[4][kW][kW];        // state with a two-volume face halo (corners unused)
   double fx[4][kP][kP + 1];   // x-face fluxes [m][y][face x]
   double fy[4][kP + 1][kP];   // y-face fluxes [m][face y][x]
   double red[kThreads / 64];
+  MlpBias bias;
   MlpLds mlp[kThreads / 64];
 };
 
@@ -263,9 +285,10 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
 #pragma unroll
     for (int m = 0; m < 4; ++m) s.q[m][hy][hx] = qin[src + m * kP * kP + sy * kP + sx];
   }
+  fill_bias(blob, s.bias, tid, kThreads);
   __syncthreads();
 
-  // ---- faces: 9 batches of 64 over the 8 waves ---------------------------
+  // ---- faces: 9 batches of 64 over the 4 waves ---------------------------
   const MlpFrags F = load_frags(blob, l);
   for (int batch = wave; batch * 64 < kNFACE; batch += kThreads / 64) {
     const int f = batch * 64 + l;
@@ -294,7 +317,7 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
         xh[4 * o + c] = ((float)fr[c] - blob[kXM + 4 * o + c]) * blob[kXS + 4 * o + c];
     }
     float out[kNO];
-    mlp64(F, s.mlp[wave], l, xh, out);
+    mlp64(F, s.bias, s.mlp[wave], l, xh, out);
     // plain flux of the face, grid axes
     double Fr[4];
     {
