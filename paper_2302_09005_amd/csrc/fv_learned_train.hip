@@ -274,12 +274,16 @@ mlp_sample_kernel(const float* __restrict__ blob, const float* __restrict__ feat
   w[kNF + 3 * kNH + j] = dd2;
 }
 
-// Gradient of one trained word (fixed-order sum over the batch) and its Adam
-// step (Kingma and Ba, 2015; beta1 0.9, beta2 0.999, eps 1e-8).
-__global__ void __launch_bounds__(256)
+// Gradient of one trained word per wave and its Adam step (Kingma and Ba,
+// 2015; beta1 0.9, beta2 0.999, eps 1e-8).  Lane i sums the samples i, i + 64,
+// ... in order, then a fixed butterfly across the wave adds the 64 partial
+// sums: the same order on every call, so training is deterministic.
+constexpr int kAdamWaves = 4;  // words per 256-thread workgroup
+__global__ void __launch_bounds__(64 * kAdamWaves)
 mlp_adam_kernel(float* __restrict__ blob, float* __restrict__ adam, int step, float lr,
                 const float* __restrict__ ws, int batch, float* __restrict__ grad_out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * kAdamWaves + (threadIdx.x >> 6);  // the same in the whole wave
   if (t >= kTrainN) return;
   const int word = kTrain0 + t;
   // which parameter: (source a, source b) offsets inside a sample's workspace
@@ -307,10 +311,13 @@ mlp_adam_kernel(float* __restrict__ blob, float* __restrict__ adam, int step, fl
     ob = -1;
   }
   float g = 0.0f;
-  for (int b = 0; b < batch; ++b) {
+  for (int b = lane; b < batch; b += 64) {
     const float* w = ws + (int64_t)b * kWs;
     g = fmaf(w[oa], ob < 0 ? 1.0f : w[ob], g);
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o, 64);
+  if (lane != 0) return;
   if (grad_out) grad_out[t] = g;
   float* m = adam;
   float* v = adam + kTrainN;
@@ -372,8 +379,8 @@ int launch_mlp_train_step(float* blob, float* adam, int step, float lr, const fl
                           float* ws, float* grad_out, hipStream_t st) {
   hipLaunchKernelGGL(mlp_sample_kernel, dim3(batch), dim3(64), 0, st, blob, feats, targ, n_rows,
                      idx, batch, ws);
-  hipLaunchKernelGGL(mlp_adam_kernel, dim3((kTrainN + 255) / 256), dim3(256), 0, st, blob, adam,
-                     step, lr, ws, batch, grad_out);
+  hipLaunchKernelGGL(mlp_adam_kernel, dim3((kTrainN + kAdamWaves - 1) / kAdamWaves),
+                     dim3(64 * kAdamWaves), 0, st, blob, adam, step, lr, ws, batch, grad_out);
   return 0;
 }
 
