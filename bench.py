@@ -432,14 +432,14 @@ def sweep_2d_p17(seed, ns, reps):
         print(json.dumps(row), flush=True)
 
 
-def learned_path(seed, train_seeds=(101, 102, 103), coarse_steps=8, epochs=20,
-                 max_samples=200000):
+def learned_path(seed, train_seeds=tuple(range(101, 133)), coarse_steps=8, epochs=30,
+                 max_samples=2000000, n_eval=4):
     """The learned face-flux correction on 2-D Euler, 256 patches of 16^2:
-    samples from 4x finer plain runs of seeded Riemann problems (faces with
-    density-jump indicator <= 0.2), minibatch-Adam training, then a held-out
-    problem run coarse with the plain and the corrected update against the
-    coarse-grained fine run; plus the time of one corrected update launch
-    against the plain gather update on the same patches."""
+    samples from 4x finer plain runs of 32 seeded Riemann problems (faces
+    with density-jump indicator <= 0.2), minibatch-Adam training, then
+    n_eval held-out problems run coarse with the plain and the corrected
+    update against the coarse-grained fine run; plus the time of one
+    corrected update launch against the plain gather update."""
     import time as _time
     import torch
     from paper_2302_09005_amd import fv, learned
@@ -462,7 +462,10 @@ def learned_path(seed, train_seeds=(101, 102, 103), coarse_steps=8, epochs=20,
     blob, losses = learned.train(f, t, epochs=epochs, batch=1024, lr=1e-3, seed=seed)
     torch.cuda.synchronize()
     t2 = _time.perf_counter()
-    ev = learned.evaluate(blob, 200 + seed, coarse_steps)
+    eval_seeds = [200 + seed + i for i in range(n_eval)]
+    evs = [learned.evaluate(blob, e, coarse_steps) for e in eval_seeds]
+    ev = evs[0]
+    ratios = np.array([np.array(e["learned"][-1]) / np.array(e["plain"][-1]) for e in evs])
     # kernel times on the coarse workload
     grid, q = W.grid_riemann_2d(learned.COARSE, learned.P, 200 + seed)
     run = learned.PatchRun(grid, q)
@@ -512,8 +515,10 @@ def learned_path(seed, train_seeds=(101, 102, 103), coarse_steps=8, epochs=20,
             "train_seeds": list(train_seeds), "coarse_steps": coarse_steps, "epochs": epochs,
             "loss_first_last": [losses[0], losses[-1]],
             "data_s": t1 - t0, "train_s": t2 - t1,
-            "eval_seed": 200 + seed,
+            "eval_seeds": eval_seeds,
             "l1_error_after_steps": {"plain": last["plain"], "learned": last["learned"]},
+            "l1_ratio_learned_over_plain": ratios.tolist(),
+            "l1_ratio_mean_per_unknown": ratios.mean(axis=0).tolist(),
             "l1_rho_per_step": {"plain": [e[0] for e in ev["plain"]],
                                 "learned": [e[0] for e in ev["learned"]]},
             "plain_update_us": plain_us, "learned_update_us": learned_us,
