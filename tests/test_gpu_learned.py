@@ -192,6 +192,32 @@ def test_learned_update_matches_oracle(bc):
     np.testing.assert_allclose(me, lam, rtol=1e-13)
 
 
+@pytest.mark.parametrize("npa", [16, 64])
+def test_learned_update_full_size_matches_oracle(npa):
+    """The corrected update at the sizes it is benchmarked on: the coarse
+    workload (16 x 16 patches of 16^2) and the 4096-patch batch, one CFL step
+    of a seeded Riemann problem (quadrant jumps fall back, smooth faces are
+    corrected) against the oracle."""
+    grid, q = _riemann(npa, 200)
+    p = _params(11)
+    dt = 0.4 * grid.dx / (2.0 * OL.max_eigenvalue_2d(q))
+    got, me = _run_learned(grid, q, p, dt)
+    ref, _, _ = OL.learned_step_2d(q, grid.dx, grid.dx, dt, p, "transmissive")
+    plain, _, _ = OL.learned_step_2d(q, grid.dx, grid.dx, dt, None, "transmissive")
+    for k in range(4):
+        corr = np.abs(ref[k] - plain[k]).max()
+        err = np.abs(got[k] - ref[k]).max()
+        _say(f"[learned update {npa}x{npa} patches] unknown {k}: err {err:.2e}, correction {corr:.2e}")
+        assert corr > 0
+        assert err <= 1e-2 * corr + 1e-12 * np.abs(ref[k]).max()
+    # per-patch maxima of the new state, on a sample of patches
+    rng = np.random.default_rng(npa)
+    for b in rng.choice(grid.n, 8, replace=False):
+        j, i = divmod(int(b), npa)
+        lam = OL.max_eigenvalue_2d(got[:, 16 * j:16 * j + 16, 16 * i:16 * i + 16])
+        np.testing.assert_allclose(me[b], lam, rtol=1e-13)
+
+
 def test_threshold_zero_and_zero_network_give_the_plain_update():
     import torch
     grid, q = _riemann(4, 8)
