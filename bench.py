@@ -192,35 +192,37 @@ def ramp(graph, seconds):
             return n
 
 
-def fp32_vs_fp64(grid, q, steps):
+def fp32_vs_fp64(grid, q, checkpoints=(1, 10, 100)):
     """Relative L2 and Linf differences (worst unknown) between the FP32 and
-    the FP64 fused steps after the same number of eager steps from the same
-    initial state."""
+    the FP64 fused steps from the same initial state, after each number of
+    eager steps in checkpoints: {steps: (l2, linf)}."""
     import torch
     from paper_2302_09005_amd import fv
-    out = {}
-    for name, dt in (("f64", np.float64), ("f32", np.float32)):
-        st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
-                        grid.pack_compact(q), dim=grid.d, p=grid.p, mode="fused", dtype=dt)
-        for _ in range(steps):
-            st.step()
-        torch.cuda.synchronize()
-        out[name] = st.state().double()
-        del st
-    a, r = out["f32"], out["f64"]
+    sts = [fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
+                      grid.pack_compact(q), dim=grid.d, p=grid.p, mode="fused", dtype=dt)
+           for dt in (np.float64, np.float32)]
     s = grid.s
-    d = (a - r).view(s, -1)
-    rv = r.view(s, -1)
-    return (float((d.norm(dim=1) / rv.norm(dim=1)).max()),
-            float((d.abs().amax(dim=1) / rv.abs().amax(dim=1)).max()))
+    out, done = {}, 0
+    for k in checkpoints:
+        for st in sts:
+            for _ in range(k - done):
+                st.step()
+        done = k
+        torch.cuda.synchronize()
+        r, a = (st.state().double() for st in sts)
+        d = (a - r).view(s, -1)
+        rv = r.view(s, -1)
+        out[k] = (float((d.norm(dim=1) / rv.norm(dim=1)).max()),
+                  float((d.abs().amax(dim=1) / rv.abs().amax(dim=1)).max()))
+    return out
 
 
-def fp32_path(grid, q, steps, warmup, ramp_s, cmp_steps=100):
+def fp32_path(grid, q, steps, warmup, ramp_s):
     """The same fused step with FP32 state (FP64 maxima / CFL), timed exactly
     as the FP64 line (eager warm-up, a graph of the timed steps, untimed
     replays for ramp_s seconds, one timed replay): throughput, kernel time,
-    roofline at the FP32 algorithmic bytes; and the relative difference to
-    the FP64 state after cmp_steps steps from the same initial state."""
+    roofline at the FP32 algorithmic bytes; and the relative differences to
+    the FP64 state after 1, 10 and 100 steps from the same initial state."""
     import torch
     from paper_2302_09005_amd import fv
     st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
@@ -245,14 +247,16 @@ def fp32_path(grid, q, steps, warmup, ramp_s, cmp_steps=100):
     torch.cuda.synchronize()
     total = t0.elapsed_time(t1)
     del graph, st
-    l2, li = fp32_vs_fp64(grid, q, cmp_steps)
+    errs = fp32_vs_fp64(grid, q)
+    l2, li = errs[100]
     bpc = algorithmic_bytes_per_cell(grid.d, grid.p, grid.s, 4)
     upd_us = total * 1e3 / steps
     return {"steps": steps, "cell_updates_per_s": grid.cells * steps / (total * 1e-3),
             "ms_per_step": total / steps, "update_us": upd_us,
             "algorithmic_bytes_per_cell": bpc,
             "update_hbm_frac": bpc * grid.cells / (upd_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-            "rel_l2_vs_fp64": l2, "rel_linf_vs_fp64": li, "compared_after_steps": cmp_steps,
+            "rel_l2_vs_fp64": l2, "rel_linf_vs_fp64": li, "compared_after_steps": 100,
+            "rel_l2_linf_vs_fp64_by_steps": {str(k): list(v) for k, v in errs.items()},
             "speedup_vs_fp64_step": None}
 
 
@@ -432,14 +436,14 @@ def sweep_2d_p17(seed, ns, reps):
         print(json.dumps(row), flush=True)
 
 
-def learned_path(seed, train_seeds=tuple(range(101, 133)), coarse_steps=8, epochs=30,
-                 max_samples=2000000, n_eval=4):
+def learned_path(seed, train_seeds=tuple(range(101, 133)), coarse_steps=8, epochs=80,
+                 max_samples=200000, n_eval=4):
     """The learned face-flux correction on 2-D Euler, 256 patches of 16^2:
-    samples from 4x finer plain runs of 32 seeded Riemann problems (faces
-    with density-jump indicator <= 0.2), minibatch-Adam training, then
-    n_eval held-out problems run coarse with the plain and the corrected
-    update against the coarse-grained fine run; plus the time of one
-    corrected update launch against the plain gather update."""
+    200k face samples drawn from 4x finer plain runs of 32 seeded Riemann
+    problems (faces with density-jump indicator <= 0.2), minibatch-Adam
+    training, then n_eval held-out problems run coarse with the plain and the
+    corrected update against the coarse-grained fine run; plus the time of
+    one corrected update launch against the plain gather update."""
     import time as _time
     import torch
     from paper_2302_09005_amd import fv, learned
