@@ -23,7 +23,7 @@ dominant kernel (the update; algorithmic bytes / its average duration, the
 timed replay divided by the steps) and the CPU oracle timed on a bounded sample
 of the same workload.
 
-    python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--ramp-s 0.3]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 20] [--ramp-s 0.3]
                     [--no-cpu-baseline]
 """
 import argparse
@@ -569,7 +569,7 @@ def copy_calibration(mib=1024, reps=5):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--ramp-s", type=float, default=0.3,
                     help="untimed graph replays before each timed replay (seconds)")
