@@ -263,6 +263,26 @@ def test_fused_step_matches_separate_launches_bitwise():
     assert st_a.lam.item() == st_a.per_patch.max().item()
 
 
+def test_fused_stepper_follows_replaced_buffers():
+    """The fused stepper's cached launch arguments follow a state buffer that
+    the caller replaced between steps (same values, new storage): bitwise the
+    same steps as an untouched stepper."""
+    import torch
+    _say("[fused stepper, state buffer replaced between steps]")
+    grid, q = W.grid_3d_random_smooth(4, 8, seed=23)
+    desc = grid.descriptors(out_halo=False, in_halo=False)
+    ref = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=3, p=8, mode="fused")
+    st = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=3, p=8, mode="fused")
+    for k in range(5):
+        ref.step()
+        if k == 2:
+            st.a = st.a.clone()
+        st.step()
+    torch.cuda.synchronize()
+    assert torch.equal(ref.state(), st.state())
+    assert torch.equal(ref.last_dt(), st.last_dt())
+
+
 def test_fused_step_nan_gives_nan_dt():
     import torch
     _say("[fused step NaN -> NaN dt]")
