@@ -132,11 +132,20 @@ def cpu_baseline(grid, flat, budget_s, max_steps):
         a, _, _ = oracle.run_steps(off, dx, a, nb, grid.d, grid.p, 1)
         steps += 1
     el = time.perf_counter() - t0
+    # the same oracle on one thread, for scale (a few steps)
+    s1 = 0
+    t1 = time.perf_counter()
+    while s1 < 3 and (s1 == 0 or time.perf_counter() - t1 < budget_s / 4):
+        a, _, _ = oracle.run_steps(off, dx, a, nb, grid.d, grid.p, 1, nthreads=1)
+        s1 += 1
+    el1 = time.perf_counter() - t1
     return {"value": grid.cells * steps / el, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{steps} full steps (CFL + update + halo fill) of the 4096x8^3 workload, "
                       f"seed 0, plain C oracle, OpenMP over patches with {threads} threads, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s",
+            "single_thread_value": grid.cells * s1 / el1,
+            "single_thread_sample": f"{s1} full steps on 1 thread, {el1:.1f} s"}
 
 
 def plain_path(grid, q, steps):
