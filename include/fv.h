@@ -374,8 +374,11 @@ int fv_mlp_fit_normalization(const float* x, int64_t x_rows, int cols, int mode,
  * (features[n_rows][16], targets[n_rows][4]): float32 forward and backward of
  * the mean-squared error of normalised targets, gradients summed in a fixed
  * order (deterministic).  adam: device float32[2 * 5508] moments (zero at
- * step 1); workspace: float32[fv_mlp_workspace_words(batch)];
- * grad_out: float32[5508] or NULL (the gradient of W1..b3). */
+ * step 1); workspace: float32[fv_mlp_workspace_words(batch)] or more, of which
+ * on return the words [W - batch, W), W = fv_mlp_workspace_words(batch), hold
+ * the per-sample mean squared errors of the minibatch (0 for a row index
+ * outside [0, n_rows)); grad_out: float32[5508] or NULL (the gradient of
+ * W1..b3). */
 int fv_mlp_workspace_words(int batch);
 int fv_mlp_train_step(float* blob, float* adam, int step, float lr, const float* features,
                       const float* targets, int64_t n_rows, const int64_t* batch_idx, int batch,

@@ -218,7 +218,9 @@ constexpr int kXM = 0, kXS = 16, kW1 = 32, kB1 = kW1 + kNH * kNF, kW2 = kB1 + kN
 static_assert(kBlob == 5548, "parameter blob layout");
 constexpr int kTrain0 = kW1, kTrainN = kYS - kW1;  // trained words: W1 .. b3
 static_assert(kTrainN == FV_MLP_TRAINED_WORDS, "trained words");
-// per-sample workspace: x_hat[16], h1[64], h2[64], d1[64], d2[64], dout[4], loss
+// workspace, field-major: field f of sample b at f * batch + b; fields x_hat[16],
+// h1[64], h2[64], d1[64], d2[64], dout[4], loss (the last batch words: the
+// per-sample mean squared error)
 constexpr int kWs = kNF + 4 * kNH + kNO + 1;
 
 // Forward and backward of one sample per 64-thread workgroup (float32).
@@ -232,11 +234,11 @@ mlp_sample_kernel(const float* __restrict__ blob, const float* __restrict__ feat
   const int64_t row0 = idx[b];
   const bool valid = row0 >= 0 && row0 < n_rows;
   const int64_t row = valid ? row0 : 0;
-  float* w = ws + (int64_t)b * kWs;
+  float* w = ws + b;  // field f at w[f * batch]
   if (j < kNF) {
     const float xh = (feats[row * kNF + j] - blob[kXM + j]) * blob[kXS + j];
     xs[j] = xh;
-    w[j] = xh;
+    w[(int64_t)j * batch] = xh;
   }
   __syncthreads();
   float a = blob[kB1 + j];
@@ -255,11 +257,11 @@ mlp_sample_kernel(const float* __restrict__ blob, const float* __restrict__ feat
     const float y = (targ[row * kNO + j] - blob[kYM + j]) / blob[kYS + j];
     const float e = valid ? o - y : 0.0f;
     dout[j] = 2.0f * e / (float)(batch * kNO);
-    w[kNF + 4 * kNH + j] = dout[j];
+    w[(int64_t)(kNF + 4 * kNH + j) * batch] = dout[j];
     xs[j] = e * e;  // per-output squared error (xs no longer needed)
   }
   __syncthreads();
-  if (j == 0) w[kNF + 4 * kNH + kNO] = (xs[0] + xs[1] + xs[2] + xs[3]) / (float)kNO;
+  if (j == 0) w[(int64_t)(kNF + 4 * kNH + kNO) * batch] = (xs[0] + xs[1] + xs[2] + xs[3]) / (float)kNO;
   float g = 0.0f;
   for (int m = 0; m < kNO; ++m) g = fmaf(dout[m], blob[kW3 + m * kNH + j], g);
   const float dd2 = g * (1.0f - v2 * v2);
@@ -268,10 +270,10 @@ mlp_sample_kernel(const float* __restrict__ blob, const float* __restrict__ feat
   g = 0.0f;
   for (int i = 0; i < kNH; ++i) g = fmaf(d2[i], blob[kW2 + i * kNH + j], g);
   const float dd1 = g * (1.0f - v1 * v1);
-  w[kNF + j] = v1;
-  w[kNF + kNH + j] = v2;
-  w[kNF + 2 * kNH + j] = dd1;
-  w[kNF + 3 * kNH + j] = dd2;
+  w[(int64_t)(kNF + j) * batch] = v1;
+  w[(int64_t)(kNF + kNH + j) * batch] = v2;
+  w[(int64_t)(kNF + 2 * kNH + j) * batch] = dd1;
+  w[(int64_t)(kNF + 3 * kNH + j) * batch] = dd2;
 }
 
 // Gradient of one trained word per wave and its Adam step (Kingma and Ba,
@@ -310,11 +312,11 @@ mlp_adam_kernel(float* __restrict__ blob, float* __restrict__ adam, int step, fl
     oa = kNF + 4 * kNH + (word - kB3);
     ob = -1;
   }
+  // field-major workspace: the lanes read consecutive samples
+  const float* wa = ws + (int64_t)oa * batch;
+  const float* wb = ob < 0 ? nullptr : ws + (int64_t)ob * batch;
   float g = 0.0f;
-  for (int b = lane; b < batch; b += 64) {
-    const float* w = ws + (int64_t)b * kWs;
-    g = fmaf(w[oa], ob < 0 ? 1.0f : w[ob], g);
-  }
+  for (int b = lane; b < batch; b += 64) g = fmaf(wa[b], wb ? wb[b] : 1.0f, g);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o, 64);
   if (lane != 0) return;

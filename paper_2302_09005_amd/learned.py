@@ -139,14 +139,15 @@ def train(features, targets, *, epochs=20, batch=1024, lr=1e-3, seed=0, init_sca
     ws = torch.empty(fv.mlp_workspace_words(batch), dtype=torch.float32, device=device)
     losses = []
     step = 0
-    wsv = ws.view(batch, -1)
+    nws = fv.mlp_workspace_words(batch)
+    loss_rows = ws[nws - batch:nws]  # per-sample squared errors of the last step
     for ep in range(epochs):
         perm = torch.from_numpy(rng.permutation(n).astype(np.int64)).to(device)
         tot, cnt = torch.zeros((), dtype=torch.float64, device=device), 0
         for i in range(0, n - batch + 1, batch):
             step += 1
             fv.mlp_train_step(blob_d, adam, step, lr, feats, targ, perm[i:i + batch], ws)
-            tot += wsv[:, -1].double().sum()
+            tot += loss_rows.double().sum()
             cnt += batch
         losses.append(float(tot.item()) / max(cnt, 1))
         if log_every and (ep + 1) % log_every == 0:

@@ -133,7 +133,8 @@ def test_train_step_gradient_and_adam():
     err = np.abs(got - ref).max() / np.abs(ref).max()
     _say(f"[train step] loss {loss:.4e}, gradient rel err {err:.2e}")
     assert err <= 1e-4
-    gl = ws.view(batch, -1)[:, -1].double().mean().item()
+    nws = fv.mlp_workspace_words(batch)
+    gl = ws[nws - batch:nws].double().mean().item()
     assert abs(gl - loss) <= 1e-5 * loss
     # Adam: the first step moves each trained word by about lr * sign(g)
     new = OL.unpack_blob(blob.cpu().numpy())
