@@ -721,7 +721,7 @@ def main():
                    "step": "fv_step_gather: update + halo exchange + next CFL step, one launch"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fv_update_kernel<double,3,8,GATHER,CFL>",
+                     "kernel": "fv_update_kernel<double,3,8,GATHER,CFL,NTS=false>",
                      "algorithmic_bytes_per_cell": bpc,
                      "kernel_avg_us": upd_ms.mean() * 1e3},
         "detail": {"update_cell_updates_per_s": cells / upd_s,

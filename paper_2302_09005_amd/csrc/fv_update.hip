@@ -74,8 +74,9 @@ struct BodyOut {
 // The update of the (up to PPW) patches of one workgroup of NTW threads, each
 // marched in ZS chunks.  b: the patch of this thread's slot (-1: none).
 // lds: PPW * ZS * SLOT elements, red: NT / 64 elements, both shared.  MODE:
-// see StepMode (kLocalDt needs a writable descriptor array and cfl).
-template <typename T, int D, int P, int NTW, int ZS, bool GATHER, int MODE>
+// see StepMode (kLocalDt needs a writable descriptor array and cfl).  NTS:
+// write the new state with non-temporal stores (the same values).
+template <typename T, int D, int P, int NTW, int ZS, bool GATHER, int MODE, bool NTS>
 __device__ __forceinline__ BodyOut update_body(
     const fv_patch* __restrict__ patches, int64_t n, const int64_t* __restrict__ neighbours,
     const T* __restrict__ qin, int64_t qin_len, T* __restrict__ qout, int64_t qout_len,
@@ -224,7 +225,13 @@ __device__ __forceinline__ BodyOut update_body(
   };
   // unknown m of the ring volume at chunk plane j in [1, PC]
   auto ld_ring = [&](int j, int m) -> T { return gring[(int64_t)m * CS + (int64_t)(j - 1) * PS]; };
-  auto st_out = [&](int pl, int m, T v) { gout[(int64_t)m * ocomp + (int64_t)pl * ostride] = v; };
+  // NTS: streaming (non-temporal) stores, for outputs too large to stay in
+  // the caches until the next step reads them
+  auto st_out = [&](int pl, int m, T v) {
+    T* dst = gout + (int64_t)m * ocomp + (int64_t)pl * ostride;
+    if constexpr (NTS) __builtin_nontemporal_store(v, dst);
+    else *dst = v;
+  };
 
   // ---- prologue: planes -1 and 0, first marching-axis face ---------------
   T qlo[S], qc[S], qnx[S], rraw[S];
@@ -463,7 +470,7 @@ __device__ __forceinline__ int64_t xcd_contiguous(int64_t w, int64_t nwg) {
   return x * q + (x < r ? x : r) + k;
 }
 
-template <typename T, int D, int P, bool GATHER, int MODE>
+template <typename T, int D, int P, bool GATHER, int MODE, bool NTS>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, Geo<D, P>::NT)))
 fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
                  const int64_t* __restrict__ neighbours,
@@ -484,7 +491,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   int64_t b = -1;
   if (slot < G::PPW && i < count) b = order ? order[order_base + i] : i;
   const BodyOut bo =
-      update_body<T, D, P, 64, G::CHUNKS, GATHER, MODE == kLocalDt ? kLocalDt : kPlain>(
+      update_body<T, D, P, 64, G::CHUNKS, GATHER, MODE == kLocalDt ? kLocalDt : kPlain, NTS>(
       patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo, gamma, dt_dev, max_eig,
       cflo.cfl, b, lds, red);
   const double lam_b = bo.lam;
@@ -575,7 +582,7 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // Two waves per SIMD: the union of the three bodies would otherwise take
 // every register and leave one.
-template <typename T>
+template <typename T, bool NTS>
 __global__ void __launch_bounds__(kMixedNT) __attribute__((amdgpu_waves_per_eu(2)))
 fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
                 const int64_t* __restrict__ neighbours, const T* __restrict__ qin,
@@ -592,19 +599,19 @@ fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
     if (un.first < 0 || un.count < 0 || un.first > n - un.count) continue;
     if (un.p == 16) {
       const int64_t b = un.count > 0 ? order[un.first] : -1;
-      update_body<T, 3, 16, kMixedNT, 1, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
+      update_body<T, 3, 16, kMixedNT, 1, true, kLocalDt, NTS>(patches, n, neighbours, qin, qin_len, qout,
                                                       qout_len, 0, gamma, nullptr, max_eig, cfl,
                                                       b, lds, red);
     } else if (un.p == 8) {
       const int slot = tid / 64;
       const int64_t b = slot < un.count ? order[un.first + slot] : -1;
-      update_body<T, 3, 8, kMixedNT, 1, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
+      update_body<T, 3, 8, kMixedNT, 1, true, kLocalDt, NTS>(patches, n, neighbours, qin, qin_len, qout,
                                                      qout_len, 0, gamma, nullptr, max_eig, cfl,
                                                      b, lds, red);
     } else if (un.p == 4) {
       const int slot = tid / 16;
       const int64_t b = slot < un.count ? order[un.first + slot] : -1;
-      update_body<T, 3, 4, kMixedNT, 1, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,
+      update_body<T, 3, 4, kMixedNT, 1, true, kLocalDt, NTS>(patches, n, neighbours, qin, qin_len, qout,
                                                      qout_len, 0, gamma, nullptr, max_eig, cfl,
                                                      b, lds, red);
     }
@@ -612,7 +619,17 @@ fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
   }
 }
 
-template <typename T, int D, int P, bool GATHER, int MODE>
+// Outputs written per launch above this many bytes use non-temporal stores.
+// MI355X keeps up to 256 MB in its Infinity Cache: a step whose input and
+// output fit there together is read back from it by the next step, and
+// streaming stores would send the output to HBM (a 4096 x 8^3 FP64 step, 84 MB
+// out, is 27 % slower with them); larger steps cannot keep their output
+// anyway, and streaming it leaves the caches to the face layers (5 % faster
+// at 32768 x 8^3).
+constexpr double kStreamingOutBytes = 128.0 * (1 << 20);
+inline bool streaming_output(double bytes) { return bytes > kStreamingOutBytes; }
+
+template <typename T, int D, int P, bool GATHER, int MODE, bool NTS>
 int launch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin, int64_t qin_len,
            T* qout, int64_t qout_len, int out_halo, T gamma, const double* dt_dev,
            double* max_eig, const CflOut& cflo, const int64_t* order, int64_t order_base,
@@ -624,7 +641,7 @@ int launch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin,
   const LaunchEvents& ev = launch_events();
   // with caller events the dispatch packet itself records them, so they time
   // the kernel's execution and nothing around it
-  hipExtLaunchKernelGGL((fv_update_kernel<T, D, P, GATHER, MODE>), dim3((unsigned)blocks),
+  hipExtLaunchKernelGGL((fv_update_kernel<T, D, P, GATHER, MODE, NTS>), dim3((unsigned)blocks),
                         dim3(G::NT), 0, st, ev.start, ev.stop, 0, patches, n, nbr, qin, qin_len,
                         qout, qout_len, out_halo, gamma, dt_dev, max_eig, cflo, order,
                         order_base, count);
@@ -636,11 +653,17 @@ int dispatch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qi
              int64_t qin_len, T* qout, int64_t qout_len, int out_halo, int dim, int p,
              double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
              const int64_t* order, int64_t order_base, int64_t count, hipStream_t st) {
-#define FV_CASE(DD, PP)                                                                     \
-  if (dim == DD && p == PP)                                                                 \
-    return launch<T, DD, PP, GATHER, MODE>(patches, n, nbr, qin, qin_len, qout, qout_len,   \
-                                           out_halo, T(gamma), dt_dev, max_eig, cflo, order, \
-                                           order_base, count, st);
+  const bool nts = streaming_output((double)count * (dim + 2) * ipow(p, dim) * sizeof(T));
+#define FV_CASE(DD, PP)                                                                        \
+  if (dim == DD && p == PP)                                                                    \
+    return nts ? launch<T, DD, PP, GATHER, MODE, true>(patches, n, nbr, qin, qin_len, qout,     \
+                                                       qout_len, out_halo, T(gamma), dt_dev,   \
+                                                       max_eig, cflo, order, order_base,       \
+                                                       count, st)                              \
+               : launch<T, DD, PP, GATHER, MODE, false>(patches, n, nbr, qin, qin_len, qout,    \
+                                                        qout_len, out_halo, T(gamma), dt_dev,  \
+                                                        max_eig, cflo, order, order_base,      \
+                                                        count, st);
   FV_CASE(2, 4)
   FV_CASE(2, 8)
   FV_CASE(2, 16)
@@ -716,13 +739,25 @@ int launch_step_local(const fv_patch* patches, int64_t n, const int64_t* neighbo
                       int64_t qout_len, double gamma, double cfl, double* max_eig, int schedule,
                       int grid, hipStream_t st) {
   const LaunchEvents& ev = launch_events();
+  // the whole step's output decides the store kind, for every launch of it
+  double out_bytes = 0.0;
+  for (int c = 0; c < 3; ++c)
+    out_bytes += (double)plan.class_count[c] * 5.0 * ipow(plan.class_p[c], 3) * sizeof(T);
+  const bool nts = streaming_output(out_bytes);
   if (schedule == FV_SCHED_PERSISTENT) {
     int64_t g = grid > 0 ? grid : plan.n_units;
     if (g > plan.n_units) g = plan.n_units;
     if (g < 1) return 0;
-    hipExtLaunchKernelGGL((fv_mixed_kernel<T>), dim3((unsigned)g), dim3(kMixedNT), 0, st,
-                          ev.start, ev.stop, 0, patches, n, neighbours, qin, qin_len, qout,
-                          qout_len, T(gamma), cfl, max_eig, plan.order, plan.units, plan.n_units);
+    if (nts)
+      hipExtLaunchKernelGGL((fv_mixed_kernel<T, true>), dim3((unsigned)g), dim3(kMixedNT), 0, st,
+                            ev.start, ev.stop, 0, patches, n, neighbours, qin, qin_len, qout,
+                            qout_len, T(gamma), cfl, max_eig, plan.order, plan.units,
+                            plan.n_units);
+    else
+      hipExtLaunchKernelGGL((fv_mixed_kernel<T, false>), dim3((unsigned)g), dim3(kMixedNT), 0,
+                            st, ev.start, ev.stop, 0, patches, n, neighbours, qin, qin_len, qout,
+                            qout_len, T(gamma), cfl, max_eig, plan.order, plan.units,
+                            plan.n_units);
     return 0;
   }
   // per size: one launch over each class's contiguous range of the sorted
@@ -737,9 +772,14 @@ int launch_step_local(const fv_patch* patches, int64_t n, const int64_t* neighbo
       int rc = FV_EUNSUPPORTED;
 #define FV_CLASS(PP)                                                                          \
   if (plan.class_p[c] == PP)                                                                  \
-    rc = launch<T, 3, PP, true, kLocalDt>(patches, n, neighbours, qin, qin_len, qout,          \
-                                          qout_len, 0, T(gamma), nullptr, max_eig, co,         \
-                                          plan.order, first + k, per, st);
+    rc = nts ? launch<T, 3, PP, true, kLocalDt, true>(patches, n, neighbours, qin, qin_len,    \
+                                                      qout, qout_len, 0, T(gamma), nullptr,   \
+                                                      max_eig, co, plan.order, first + k,     \
+                                                      per, st)                                \
+             : launch<T, 3, PP, true, kLocalDt, false>(patches, n, neighbours, qin, qin_len,   \
+                                                       qout, qout_len, 0, T(gamma), nullptr,  \
+                                                       max_eig, co, plan.order, first + k,    \
+                                                       per, st);
       FV_CLASS(4)
       FV_CLASS(8)
       FV_CLASS(16)

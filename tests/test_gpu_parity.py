@@ -283,6 +283,28 @@ def test_fused_stepper_follows_replaced_buffers():
     assert torch.equal(ref.last_dt(), st.last_dt())
 
 
+def test_streaming_stores_give_the_same_bits():
+    """A launch whose output exceeds the streaming threshold (128 MiB) writes
+    with non-temporal stores; the same patches updated as two smaller launches
+    (ordinary stores) give the same bits."""
+    import torch
+    _say("[streaming stores: 9261 x 8^3 in one launch vs two]")
+    grid, q = W.grid_3d_random_smooth(21, 8, seed=29)
+    flat = grid.pack(q)
+    desc = grid.descriptors(dt=first_dt(grid, flat), out_halo=False)
+    assert desc.shape[0] * 5 * 512 * 8 > 128 * 2 ** 20 > (desc.shape[0] // 2 + 1) * 5 * 512 * 8
+    qin = to_dev(flat)
+    outs = []
+    for parts in ((desc,), (desc[: grid.n // 2], desc[grid.n // 2:])):
+        qout = torch.full((grid.buffer_len(False),), -123.0, dtype=torch.float64, device="cuda")
+        for part in parts:
+            fv.batch_update(fv.upload_patches(part), qin, qout, dim=3, p=8, q_out_halo=False)
+        torch.cuda.synchronize()
+        outs.append(qout)
+    assert torch.equal(outs[0], outs[1])
+    assert not bool((outs[0] == -123.0).any())
+
+
 def test_fused_step_nan_gives_nan_dt():
     import torch
     _say("[fused step NaN -> NaN dt]")
