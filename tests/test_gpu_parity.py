@@ -211,6 +211,20 @@ def test_c2_full_size_ten_steps_with_halo_and_cfl(c2, mode):
         assert np.abs(full[m] - ref[m]).max() <= TOL * np.abs(ref[m]).max()
 
 
+def test_c2_full_size_hundred_fused_steps(c2):
+    """The benchmarked run itself: 100 fused steps of 4096 x 8^3 (device CFL
+    every step) against 100 oracle steps, and the dt sequence."""
+    _say("[c2 3d 4096x8^3 hundred fused steps]")
+    grid, flat = c2
+    got, dts, _ = run_gpu_steps(grid, grid.unpack(flat), 100, "fused")
+    ref, _, dts_ref = oracle.run_steps(grid.offsets(), np.full((grid.n, 3), grid.dx), flat,
+                                       grid.neighbours(), 3, 8, 100, nthreads=0)
+    np.testing.assert_allclose(dts, dts_ref, rtol=1e-12)
+    err = normwise(got, grid.unpack(ref), 5)
+    _say(f"    err after 100 steps = {err:.3e}")
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("d,p,counts,bc", [
     (3, 8, (4, 3, 2), ("periodic",) * 3),
     (3, 8, (3, 2, 2), ("transmissive", "periodic", "transmissive")),
