@@ -22,9 +22,14 @@ namespace fvk {
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 // Chunks along the marching axis per patch in the single-size update
-// kernels (each chunk marches P / ZS planes in a wave of its own).
+// kernels: each chunk marches P / ZS planes, in a wave of its own when a
+// plane has 64 volumes, else in its own group of lanes of the patch's wave.
+// 2-D patches of 16^2 and 32^2 fill one wave that way (4 and 2 chunks), so a
+// patch is marched in 4 or 16 rows instead of 16 or 32.
 template <int D, int P>
-constexpr int zsplit() { return D == 3 && P == 8 ? FV_ZSPLIT_3D8 : 1; }
+constexpr int zsplit() {
+  return D == 3 && P == 8 ? FV_ZSPLIT_3D8 : D == 2 && P == 16 ? 4 : D == 2 && P == 32 ? 2 : 1;
+}
 
 // Geometry of a D-dimensional patch of P^D volumes with a halo of one volume,
 // and of the plane-marching update that processes it.
@@ -60,9 +65,12 @@ struct Geo {
   static constexpr int FST = NF + FV_LDS_FPAD;
   static constexpr int CELLBUF = NV * CST;
   static constexpr int FACEBUF = (D - 1) * S * FST;
-  static constexpr int SLOT = CELLBUF > FACEBUF ? CELLBUF : FACEBUF;  // LDS elements per patch
+  static constexpr int SLOT = CELLBUF > FACEBUF ? CELLBUF : FACEBUF;  // LDS elements per chunk
+  // reduction slots: one per wave of the workgroup, or one per chunk
+  static constexpr int NRED = NT / 64 > PPW * ZS ? NT / 64 : PPW * ZS;
   static_assert(RING <= LANES, "every ring volume needs its own lane");
-  static_assert(P % ZS == 0 && (ZS == 1 || LANES == 64), "chunks are whole planes of one wave");
+  static_assert(P % ZS == 0 && (ZS == 1 || LANES == 64 || ZS * LANES <= 64),
+                "chunks are whole waves, or lane groups of one wave");
   static_assert(NEXTRA <= LANES, "every high-boundary face needs its own lane");
 };
 

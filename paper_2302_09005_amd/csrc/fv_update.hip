@@ -73,7 +73,7 @@ struct BodyOut {
 
 // The update of the (up to PPW) patches of one workgroup of NTW threads, each
 // marched in ZS chunks.  b: the patch of this thread's slot (-1: none).
-// lds: PPW * ZS * SLOT elements, red: NT / 64 elements, both shared.  MODE:
+// lds: PPW * ZS * SLOT elements, red: Geo::NRED elements, both shared.  MODE:
 // see StepMode (kLocalDt needs a writable descriptor array and cfl).  NTS:
 // write the new state with non-temporal stores (the same values).
 template <typename T, int D, int P, int NTW, int ZS, bool GATHER, int MODE, bool NTS>
@@ -427,12 +427,12 @@ __device__ __forceinline__ BodyOut update_body(
         for (int w = 1; w < LANES / 64; ++w) lam = nanmax_pos(lam, red[w]);
       }
     } else if constexpr (ZS > 1) {
-      // one wave per chunk: fold the chunks of each patch
-      if (l == 0) red[tid >> 6] = lam;
+      // fold the chunks of each patch (whole waves, or lane groups of one)
+      if (l == 0) red[slot * ZS + chunk] = lam;
       __syncthreads();
       if (lead) {
 #pragma unroll
-        for (int c = 1; c < ZS; ++c) lam = nanmax_pos(lam, red[(tid >> 6) + c]);
+        for (int c = 1; c < ZS; ++c) lam = nanmax_pos(lam, red[slot * ZS + c]);
       }
     }
   } else {
@@ -481,7 +481,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
                  int64_t count) {
   using G = Geo<D, P>;
   __shared__ T lds[G::PPW * G::CHUNKS * G::SLOT];
-  __shared__ T red[G::NT / 64];
+  __shared__ T red[G::NRED];
   const int tid = threadIdx.x;
   const int slot = G::PPW == 1 ? 0 : tid / G::TPP;
   // the patch of this thread's slot: launch item i is patch i, or the
