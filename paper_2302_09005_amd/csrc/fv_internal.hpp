@@ -22,13 +22,18 @@ namespace fvk {
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
 // Chunks along the marching axis per patch in the single-size update
-// kernels: each chunk marches P / ZS planes, in a wave of its own when a
-// plane has 64 volumes, else in its own group of lanes of the patch's wave.
-// 2-D patches of 16^2 and 32^2 fill one wave that way (4 and 2 chunks), so a
-// patch is marched in 4 or 16 rows instead of 16 or 32.
+// kernels: each chunk marches ceil(P / ZS) planes (the last one fewer when ZS
+// does not divide P), in a wave of its own when a plane has 64 volumes, else
+// in its own group of lanes of the patch's wave.  2-D patches of 16^2, 17^2
+// and 32^2 fill one wave that way (4, 3 and 2 chunks), so a patch is marched
+// in 4, 6 or 16 rows instead of 16, 17 or 32.
 template <int D, int P>
 constexpr int zsplit() {
-  return D == 3 && P == 8 ? FV_ZSPLIT_3D8 : D == 2 && P == 16 ? 4 : D == 2 && P == 32 ? 2 : 1;
+  return D == 3 && P == 8    ? FV_ZSPLIT_3D8
+         : D == 2 && P == 16 ? 4
+         : D == 2 && P == 17 ? 3
+         : D == 2 && P == 32 ? 2
+                             : 1;
 }
 
 // Geometry of a D-dimensional patch of P^D volumes with a halo of one volume,
@@ -50,7 +55,7 @@ struct Geo {
   static constexpr int SMO = ipow(P, D - 1);         // compact stride of the marching axis
   static constexpr int LANES = ipow(P, D - 1);       // lanes per chunk (one column each)
   static constexpr int CHUNKS = ZS;                  // chunks per patch
-  static constexpr int PC = P / ZS;                  // planes per chunk
+  static constexpr int PC = (P + ZS - 1) / ZS;       // planes per chunk (the last: P - (ZS-1) PC)
   static constexpr int TPP = ZS * LANES;             // threads per patch
   static constexpr int PPW = TPP >= NTW ? 1 : NTW / TPP;  // patches per workgroup
   static constexpr int NT = ((PPW * TPP + 63) / 64) * 64; // workgroup size
@@ -69,8 +74,10 @@ struct Geo {
   // reduction slots: one per wave of the workgroup, or one per chunk
   static constexpr int NRED = NT / 64 > PPW * ZS ? NT / 64 : PPW * ZS;
   static_assert(RING <= LANES, "every ring volume needs its own lane");
-  static_assert(P % ZS == 0 && (ZS == 1 || LANES == 64 || ZS * LANES <= 64),
+  static_assert(ZS == 1 || LANES == 64 || ZS * LANES <= 64,
                 "chunks are whole waves, or lane groups of one wave");
+  static_assert(P % ZS == 0 || ZS * LANES <= 64, "uneven chunks only as lane groups of one wave");
+  static_assert((ZS - 1) * PC < P, "every chunk has a plane");
   static_assert(NEXTRA <= LANES, "every high-boundary face needs its own lane");
 };
 

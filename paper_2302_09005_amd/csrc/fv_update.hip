@@ -84,7 +84,8 @@ __device__ __forceinline__ BodyOut update_body(
     double cfl, int64_t b, T* __restrict__ lds, T* __restrict__ red) {
   using G = Geo<D, P, NTW, ZS>;
   constexpr int S = G::S;
-  constexpr int PC = G::PC;  // planes of this thread's chunk
+  constexpr int PC = G::PC;  // planes of a chunk (the last chunk may have fewer)
+  constexpr bool UNEVEN = P % ZS != 0;
   constexpr int K = D - 1;  // marching axis
   constexpr int W = G::W;
   constexpr int LANES = G::LANES;
@@ -100,7 +101,12 @@ __device__ __forceinline__ BodyOut update_body(
   const int chunk = ZS == 1 ? 0 : tp / LANES;
   const int l = ZS == 1 ? tp : tp - chunk * LANES;
   const int p0 = chunk * PC;  // first plane of the chunk
-  const bool in_range = (G::PPW == 1 || slot < G::PPW) && b >= 0 && b < n;
+  // planes of this chunk (PC, or fewer for the last chunk of an uneven split)
+  const int nrows = UNEVEN ? (P - p0 < PC ? P - p0 : PC) : PC;
+  // threads past the workgroup's patches (a lone patch of fewer threads than
+  // the workgroup, e.g. 3 chunks of 17 lanes in a wave) take no part
+  const bool in_patch = G::PPW * G::TPP == G::NT || tid < G::PPW * G::TPP;
+  const bool in_range = in_patch && (G::PPW == 1 || slot < G::PPW) && b >= 0 && b < n;
   const bool lead = in_range && l == 0 && chunk == 0;  // writes the patch results
   const int x = l % P;
   const int y = (D == 3) ? l / P : 0;
@@ -185,7 +191,8 @@ __device__ __forceinline__ BodyOut update_body(
     dt_used = uni(dt_used);
     t_used = uni(t_used);
   }
-  T* cell = lds + (ok ? (slot * ZS + chunk) * G::SLOT : 0);  // plane buffer [NV][NCELL]
+  // plane buffer [NV][NCELL]
+  T* cell = lds + (ok && in_patch ? (slot * ZS + chunk) * G::SLOT : 0);
   T* face = cell;                             // face buffers, same storage
 
   // in-plane element index of the own column (compact and halo'd) and of
@@ -206,24 +213,25 @@ __device__ __forceinline__ BodyOut update_body(
   const int64_t ostride = out_halo ? G::SM : G::SMO;
   const int64_t ocomp = out_halo ? G::VIN : G::VOUT;
 
-  // the chunk's own planes p0 .. p0+PC-1 (storage plane j = 1 + plane in a
+  // the chunk's own planes p0 .. p0+nrows-1 (storage plane j = 1 + plane in a
   // halo'd block, = plane in a compact one), the plane below and the plane
   // above it (halo planes, or planes of the neighbouring chunks)
   const int64_t jin = GATHER ? p0 : p0 + 1;
   const T* gin = qin + off_in + col_in + jin * PS;
   const T* glo = (GATHER && chunk == 0) ? qin + lo_base + col_c : gin - PS;
-  const T* ghi = (GATHER && chunk == ZS - 1) ? qin + hi_base + col_c : gin + (int64_t)PC * PS;
+  const T* ghi =
+      (GATHER && chunk == ZS - 1) ? qin + hi_base + col_c : gin + (int64_t)nrows * PS;
   const T* gring = (GATHER ? qin + ring_src : qin + off_in + ring_h + PS) + (int64_t)p0 * PS;
   T* gout = qout + off_out + col_out + (int64_t)p0 * ostride;
 
-  // unknown m of the own column at chunk storage plane j in [0, PC+1] (0 and
-  // PC+1: the planes below and above the chunk)
+  // unknown m of the own column at chunk storage plane j in [0, nrows+1] (0
+  // and nrows+1: the planes below and above the chunk)
   auto ld_own = [&](int j, int m) -> T {
     if (j == 0) return glo[(int64_t)m * CS];
-    if (j == PC + 1) return ghi[(int64_t)m * CS];
+    if (j == nrows + 1) return ghi[(int64_t)m * CS];
     return gin[(int64_t)m * CS + (int64_t)(j - 1) * PS];
   };
-  // unknown m of the ring volume at chunk plane j in [1, PC]
+  // unknown m of the ring volume at chunk plane j in [1, nrows]
   auto ld_ring = [&](int j, int m) -> T { return gring[(int64_t)m * CS + (int64_t)(j - 1) * PS]; };
   // NTS: streaming (non-temporal) stores, for outputs too large to stay in
   // the caches until the next step reads them
@@ -243,7 +251,7 @@ __device__ __forceinline__ BodyOut update_body(
     rraw[m] = T(1);
   }
   // a patch that failed its checks skips all work (its max_eig becomes NaN)
-  const bool act = ok;
+  const bool act = ok && in_patch;
   if (act) {
 #pragma unroll
     for (int m = 0; m < S; ++m) {
@@ -275,6 +283,8 @@ __device__ __forceinline__ BodyOut update_body(
   constexpr int UNROLL = PC <= 8 ? PC : 2;
 #pragma unroll UNROLL
   for (int pl = 0; pl < PC; ++pl) {
+    // the last chunk of an uneven split idles through its missing planes
+    const bool live = !UNEVEN || pl < nrows;
     // loads for the next plane: its own volumes (needed for the
     // marching-axis face in D) and its ring (needed in the next A)
     T rnext[S];
@@ -283,8 +293,8 @@ __device__ __forceinline__ BodyOut update_body(
       rnext[m] = rraw[m];
       qnx[m] = qc[m];
     }
-    if (act) {
-      if (pl + 1 < PC) {
+    if (act && live) {
+      if (pl + 1 < nrows) {
 #pragma unroll
         for (int m = 0; m < S; ++m) rnext[m] = ld_ring(pl + 2, m);
       }
@@ -292,7 +302,7 @@ __device__ __forceinline__ BodyOut update_body(
       for (int m = 0; m < S; ++m) qnx[m] = ld_own(pl + 2, m);
     }
     // A. publish own and ring volumes of this plane
-    if (act) {
+    if (act && live) {
 #pragma unroll
       for (int m = 0; m < S; ++m) cell[m * NCELL + l] = qc[m];
       cell[(S + 0) * NCELL + l] = wc.ir;
@@ -314,7 +324,7 @@ __device__ __forceinline__ BodyOut update_body(
     // are then live while no other face result is, which keeps the body at
     // 4 waves per SIMD for 3-D 8^3 FP64 (126 VGPRs; 168 the other way round).
     T Fl0[S], Fl1[S], Fx[S];
-    if (act) {
+    if (act && live) {
       if (l < G::NEXTRA) {
         // high-boundary face: interior volume at coordinate P-1 against the
         // ring.  A y face reads its two in-plane momenta swapped, so that one
@@ -362,7 +372,7 @@ __device__ __forceinline__ BodyOut update_body(
     __syncthreads();
 
     // C. publish face fluxes: face[k][m][index]
-    if (act) {
+    if (act && live) {
 #pragma unroll
       for (int m = 0; m < S; ++m) face[m * NF + fx_lo] = Fl0[m];
       if constexpr (D == 3) {
@@ -383,7 +393,7 @@ __device__ __forceinline__ BodyOut update_body(
     // The x and y terms of the update are applied first, so the in-plane face
     // fluxes are dead before the marching-axis face is evaluated (same
     // operations in the same order as one expression per unknown).
-    if (act) {
+    if (act && live) {
       T v[S];
 #pragma unroll
       for (int m = 0; m < S; ++m) {
@@ -428,7 +438,7 @@ __device__ __forceinline__ BodyOut update_body(
       }
     } else if constexpr (ZS > 1) {
       // fold the chunks of each patch (whole waves, or lane groups of one)
-      if (l == 0) red[slot * ZS + chunk] = lam;
+      if (l == 0 && in_patch) red[slot * ZS + chunk] = lam;
       __syncthreads();
       if (lead) {
 #pragma unroll
@@ -436,11 +446,12 @@ __device__ __forceinline__ BodyOut update_body(
       }
     }
   } else {
-    // odd cross-sections (e.g. 17 lanes): gather through LDS
+    // odd cross-sections (e.g. 17 lanes): gather the lanes of every chunk
+    // of the patch through LDS
     lds[tid < G::PPW * G::SLOT ? tid : 0] = lam;
     __syncthreads();
-    if (in_range && l == 0) {
-      for (int i = 1; i < LANES; ++i) lam = nanmax_pos(lam, lds[slot * LANES + i]);
+    if (lead) {
+      for (int i = 1; i < G::TPP; ++i) lam = nanmax_pos(lam, lds[slot * G::TPP + i]);
     }
   }
   const double lam_b = ok ? double(lam) : __builtin_nan("");

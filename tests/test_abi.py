@@ -139,7 +139,8 @@ def test_step_workspace_size_and_rejection_on_host():
     assert fv.step_workspace_words(4096, 3, 8) == 32 * (1 + 64)
     assert fv.step_workspace_words(64, 2, 16) == 32 * 2   # one patch (4 row chunks) per workgroup
     assert fv.step_workspace_words(100, 2, 16) == 32 * 3  # 100 workgroups: two groups + top
-    assert fv.step_workspace_words(100, 2, 17) == 32 * 2  # 3 patches per workgroup: 34
+    assert fv.step_workspace_words(100, 2, 17) == 32 * 3  # one patch (3 row chunks) each
+    assert fv.step_workspace_words(100, 2, 8) == 32 * 2   # 8 patches per workgroup: 13
     assert fv.step_workspace_words(0, 3, 8) == 0 and fv.step_workspace_words(10, 3, 5) == 0
     args = [0x1000, 4096, 0x2000, 0x10000, 1000, 0x100000, 1000, 3, 8, 5, 1.4, 0.4, 0x3000, None,
             0x4000]
