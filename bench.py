@@ -30,6 +30,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -55,10 +56,17 @@ def algorithmic_bytes_per_cell(d, p, s, elem):
 
 
 def kernel_source_hash():
+    """First 16 hex digits of a SHA-256 over the update kernel sources with
+    comments and blank lines removed (a comment edit keeps the measured
+    traffic valid; any code change invalidates it)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

@@ -7,7 +7,10 @@
 // and store is a whole plane of one unknown: contiguous rows of P elements,
 // unit stride across lanes (coalesced SoA traffic).  A 3-D 8^3 patch is one
 // wave64; smaller cross-sections pack several patches into one wave, larger
-// ones span several waves of one workgroup.
+// ones span several waves of one workgroup.  A patch may also be marched in
+// chunks of planes side by side (2-D 16^2, 17^2 and 32^2 patches: 4, 3 and 2
+// chunks, each a lane group of one wave), each chunk recomputing the face
+// below its first plane; the results do not depend on the split.
 //
 // Per plane:
 //   A. each lane publishes its volume (q, 1/rho, p, c) to LDS; lanes
@@ -35,7 +38,9 @@
 //     no separate halo-fill pass and no halo storage.  Results are identical.
 //
 // The per-patch maximum is reduced across the patch's lanes with wave
-// shuffles (and LDS across waves when a patch spans several waves).
+// shuffles (and LDS across waves or chunks).  Launches that write more than
+// 128 MB store the new state with non-temporal stores (a second instance of
+// each kernel; same values).
 #include <hip/hip_ext.h>
 
 #include "fv_euler.hpp"

@@ -75,3 +75,15 @@ def test_ramp_replays_until_the_time_has_passed(monkeypatch, n):
     got = bench.ramp(graph, float(n))
     assert got == len(calls) == n
     assert bench.ramp(graph, 0.0) == 1
+
+
+def test_source_hash_ignores_comments_only(monkeypatch, tmp_path):
+    """The traffic summary stays valid across comment edits, not code edits."""
+    def digest(text):
+        (tmp_path / "k.hip").write_text(text)
+        monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+        monkeypatch.setattr(bench, "KERNEL_SOURCES", ["k.hip"])
+        return bench.kernel_source_hash()
+    base = digest("int f(int x) {\n  return x + 1;\n}\n")
+    assert digest("// about f\nint f(int x) {  /* one more */\n\n  return x + 1;  // done\n}\n") == base
+    assert digest("int f(int x) {\n  return x + 2;\n}\n") != base
