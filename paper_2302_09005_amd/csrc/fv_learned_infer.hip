@@ -209,25 +209,29 @@ constexpr int kP = 16, kH = 2, kW = kP + 2 * kH;  // volumes per axis with the h
 constexpr int kNXF = (kP + 1) * kP;              // x faces (= y faces) per patch
 constexpr int kNFACE = 2 * kNXF;                 // 544
 constexpr int kVolThreads = kP * kP;  // one thread per volume in the update
-constexpr int kThreads = 256;         // four waves share the 9 face batches
-
+// Workgroup size: NTH threads (4 or 8 waves) share the 9 face batches.  Eight
+// waves shorten a patch's face phase (at most 1.5 batches per wave instead of
+// 2.5) for small launches; four waves fit three workgroups per CU for large
+// ones.
+template <int NTH>
 struct PatchLds {
   double q[4][kW][kW];        // state with a two-volume face halo (corners unused)
   double fx[4][kP][kP + 1];   // x-face fluxes [m][y][face x]
   double fy[4][kP + 1][kP];   // y-face fluxes [m][face y][x]
-  double red[kThreads / 64];
+  double red[NTH / 64];
   MlpBias bias;
-  MlpLds mlp[kThreads / 64];
+  MlpLds mlp[NTH / 64];
 };
 
-__global__ void __launch_bounds__(kThreads)
+template <int NTH>
+__global__ void __launch_bounds__(NTH)
 learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
                       const int64_t* __restrict__ neighbours, const double* __restrict__ qin,
                       int64_t qin_len, double* __restrict__ qout, int64_t qout_len,
                       double gamma, const double* __restrict__ dt_dev,
                       const float* __restrict__ blob, double threshold,
                       double* __restrict__ max_eig) {
-  __shared__ PatchLds s;
+  __shared__ PatchLds<NTH> s;
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
   const int64_t b = blockIdx.x;
   constexpr int64_t blk = 4 * kP * kP;
@@ -285,12 +289,12 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
 #pragma unroll
     for (int m = 0; m < 4; ++m) s.q[m][hy][hx] = qin[src + m * kP * kP + sy * kP + sx];
   }
-  fill_bias(blob, s.bias, tid, kThreads);
+  fill_bias(blob, s.bias, tid, NTH);
   __syncthreads();
 
-  // ---- faces: 9 batches of 64 over the 4 waves ---------------------------
+  // ---- faces: 9 batches of 64 over the NTH / 64 waves ---------------------
   const MlpFrags F = load_frags(blob, l);
-  for (int batch = wave; batch * 64 < kNFACE; batch += kThreads / 64) {
+  for (int batch = wave; batch * 64 < kNFACE; batch += NTH / 64) {
     const int f = batch * 64 + l;
     const bool real = f < kNFACE;
     const int ff = real ? f : kNFACE - 1;
@@ -364,7 +368,7 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   __syncthreads();
   if (tid == 0 && max_eig) {
     double mx = s.red[0];
-    for (int w = 1; w < kThreads / 64; ++w) mx = nanmax_pos(mx, s.red[w]);
+    for (int w = 1; w < NTH / 64; ++w) mx = nanmax_pos(mx, s.red[w]);
     max_eig[b] = mx;
   }
 }
@@ -386,9 +390,19 @@ int launch_update_learned_2d(const fv_patch* patches, int64_t n, const int64_t* 
                              double threshold, double* max_eig, hipStream_t st) {
   if (n == 0) return 0;
   const LaunchEvents& ev = launch_events();
-  hipExtLaunchKernelGGL(learned_update_kernel, dim3((unsigned)n), dim3(kThreads), 0, st, ev.start,
-                        ev.stop, 0, patches, n, neighbours, qin, qin_len, qout, qout_len, gamma,
-                        dt_dev, blob, threshold, max_eig);
+  // eight waves per patch while every patch has a CU of its own
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 0;
+  if (n <= cus)
+    hipExtLaunchKernelGGL(learned_update_kernel<512>, dim3((unsigned)n), dim3(512), 0, st,
+                          ev.start, ev.stop, 0, patches, n, neighbours, qin, qin_len, qout,
+                          qout_len, gamma, dt_dev, blob, threshold, max_eig);
+  else
+    hipExtLaunchKernelGGL(learned_update_kernel<256>, dim3((unsigned)n), dim3(256), 0, st,
+                          ev.start, ev.stop, 0, patches, n, neighbours, qin, qin_len, qout,
+                          qout_len, gamma, dt_dev, blob, threshold, max_eig);
   return 0;
 }
 
