@@ -624,6 +624,27 @@ def test_ragged_batch_sizes(n):
     np.testing.assert_allclose(me, me_ref, rtol=LAM_TOL)
 
 
+@pytest.mark.parametrize("p", [16, 17, 32])
+@pytest.mark.parametrize("n", [1, 2, 7])
+def test_ragged_batches_of_row_chunked_2d_patches(p, n):
+    """2-D patches marched in row chunks (uneven for 17^2): the first n of a
+    4 x 2 grid, one launch, against the oracle; untouched blocks stay."""
+    _say(f"[row-chunked 2-D p={p} n={n}]")
+    rng = np.random.default_rng(10 * p + n)
+    grid = W.PatchGrid(2, p, (4, 2), 1.0 / (4 * p))
+    shape = grid.shape
+    q = W.to_conserved(rng.uniform(0.5, 1.5, shape), [rng.uniform(-0.5, 0.5, shape) for _ in range(2)],
+                       rng.uniform(0.5, 2.0, shape))
+    flat = grid.pack(q)
+    desc = grid.descriptors(dt=first_dt(grid, flat), out_halo=False)[:n].copy()
+    got, me = gpu_step(grid, flat, desc, out_halo=False)
+    ref, me_ref = oracle_step(grid, flat, desc, out_halo=False)
+    m = ref != -123.0
+    assert np.abs(got[m] - ref[m]).max() <= TOL * np.abs(ref[m]).max()
+    assert ((got == -123.0) == (ref == -123.0)).all()
+    np.testing.assert_allclose(me, me_ref, rtol=LAM_TOL)
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_fused_steps_in_a_graph_match_eager_bitwise(dtype):
     """The fused step captured as a HIP graph (how the benchmark times it),
