@@ -100,6 +100,45 @@ __device__ MlpFrags load_frags(const float* __restrict__ blob, int l) {
   return F;
 }
 
+// The fragments of all 64 lanes as one table [14][64] of bfloat16 x 8 (w1[2],
+// w2[2][4], w3[4]), built once per workgroup by all its threads (each lane
+// fragment from 8 blob words), then read back by every wave: 896 fragment
+// builds per workgroup instead of 14 per lane of every wave.
+constexpr int kFrags = 14;
+__device__ void stage_frags(const float* __restrict__ blob, bf16x8* table, int tid, int nthreads) {
+  for (int i = tid; i < kFrags * 64; i += nthreads) {
+    const int f = i >> 6, lane = i & 63;
+    const int j = lane & 31, h = lane >> 5;
+    float v[8];
+    if (f < 2) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = blob[kW1 + (32 * f + j) * kNF + 8 * h + e];
+    } else if (f < 10) {
+      const int mt = (f - 2) >> 2, ks = (f - 2) & 3;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = blob[kW2 + (32 * mt + j) * kNH + unit_of(ks, h, e)];
+    } else {
+      const int ks = f - 10;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = j < kNO ? blob[kW3 + j * kNH + unit_of(ks, h, e)] : 0.0f;
+    }
+    table[i] = to_bf16x8(v);
+  }
+}
+
+__device__ MlpFrags frags_from_table(const bf16x8* table, int l) {
+  MlpFrags F;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    F.w1[mt] = table[mt * 64 + l];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) F.w2[mt][ks] = table[(2 + mt * 4 + ks) * 64 + l];
+  }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) F.w3[ks] = table[(10 + ks) * 64 + l];
+  return F;
+}
+
 // Biases in accumulator order, [unit tile][h][register]: a layer starts its
 // sums from them.  One copy per workgroup, filled by fill_bias.
 struct MlpBias {
@@ -216,8 +255,13 @@ constexpr int kVolThreads = kP * kP;  // one thread per volume in the update
 template <int NTH>
 struct PatchLds {
   double q[4][kW][kW];        // state with a two-volume face halo (corners unused)
-  double fx[4][kP][kP + 1];   // x-face fluxes [m][y][face x]
-  double fy[4][kP + 1][kP];   // y-face fluxes [m][face y][x]
+  union {
+    struct {
+      double fx[4][kP][kP + 1];   // x-face fluxes [m][y][face x]
+      double fy[4][kP + 1][kP];   // y-face fluxes [m][face y][x]
+    };
+    bf16x8 frags[kFrags * 64];  // network fragments, read by every wave before any flux
+  };
   double red[NTH / 64];
   MlpBias bias;
   MlpLds mlp[NTH / 64];
@@ -290,10 +334,12 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
     for (int m = 0; m < 4; ++m) s.q[m][hy][hx] = qin[src + m * kP * kP + sy * kP + sx];
   }
   fill_bias(blob, s.bias, tid, NTH);
+  stage_frags(blob, s.frags, tid, NTH);
   __syncthreads();
+  const MlpFrags F = frags_from_table(s.frags, l);
+  __syncthreads();  // the flux buffers reuse the fragment table
 
   // ---- faces: 9 batches of 64 over the NTH / 64 waves ---------------------
-  const MlpFrags F = load_frags(blob, l);
   for (int batch = wave; batch * 64 < kNFACE; batch += NTH / 64) {
     const int f = batch * 64 + l;
     const bool real = f < kNFACE;
