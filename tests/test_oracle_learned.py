@@ -246,3 +246,80 @@ def test_network_definition_against_torch_layers():
     pt = dict(p32)
     pt["w2"] = p32["w2"].T.copy()
     assert np.abs(L.mlp_forward(x.astype(np.float32), pt) - o64).max() > 0.1 * np.abs(o64).max()
+
+
+# ---------------------------------------------------------------------------
+# face frame and stencil order, pinned by hand values
+# ---------------------------------------------------------------------------
+def _labelled_grid(ny=4, nx=5):
+    """q[m, y, x] = 1000 m + 10 y + x + 1: every value names its volume."""
+    m, y, x = np.meshgrid(np.arange(4), np.arange(ny), np.arange(nx), indexing="ij")
+    return (1000.0 * m + 10.0 * y + x + 1.0)
+
+
+def test_face_features_match_hand_values():
+    """The 16 features of chosen x and y faces (interior, periodic and
+    transmissive boundaries) equal the hand-written stencil of
+    tests/golden/learned_face_stencil.txt: volumes i-2 .. i+1 along the
+    normal, each as (rho, j_n, j_t, E).  A reversed stencil, a swapped j_n /
+    j_t or a wrong halo rule fails here."""
+    from conftest import read_golden
+    q = _labelled_grid()
+    rows = read_golden("learned_face_stencil.txt")
+    assert len(rows) == 7
+    for name, vals in rows:
+        bc = ("periodic", "transmissive")[int(vals[0])]
+        k, row, col = int(vals[1]), int(vals[2]), int(vals[3])
+        want = np.array(vals[4:])
+        assert want.size == 16, name
+        Lq, Rq, feats, ind = L.face_data(q, k, bc)
+        assert feats.shape == ((16, 4, 6) if k == 0 else (16, 5, 5)), name
+        np.testing.assert_array_equal(feats[:, row, col], want, err_msg=name)
+        # L and R are the two middle volumes (grid axes), and the indicator
+        # compares their densities
+        assert Lq[0, row, col] == want[4] and Rq[0, row, col] == want[8], name
+        assert ind[row, col] == abs(want[8] - want[4]) / min(want[4], want[8]), name
+
+
+def test_face_frame_of_each_axis():
+    """to_face_frame reads (rho, j_n, j_t, E): j_x first on x faces, j_y first
+    on y faces."""
+    q = np.array([1.0, 2.0, 3.0, 4.0])
+    np.testing.assert_array_equal(L.to_face_frame(q, 0), [1.0, 2.0, 3.0, 4.0])
+    np.testing.assert_array_equal(L.to_face_frame(q, 1), [1.0, 3.0, 2.0, 4.0])
+
+
+def test_targets_are_face_frame_differences():
+    """A reference flux that exceeds the coarse Rusanov flux by D (grid axes:
+    rho, j_x, j_y, E) gives the target D on x faces and (D_rho, D_jy, D_jx,
+    D_E) on y faces, x faces first in row-major order."""
+    qc = _random_grid(6, 41)
+    D = np.array([0.5, -1.25, 2.0, 4.0])
+    stars = []
+    for k in (0, 1):
+        Lq, Rq, _, _ = L.face_data(qc, k, "periodic")
+        stars.append(L.rusanov_2d(Lq, Rq, k) + D[:, None, None])
+    feats, targ, ind = L.face_samples(qc, stars[0], stars[1], "periodic")
+    nx_faces = 6 * 7
+    assert feats.shape == (2 * nx_faces, 16) and targ.shape == (2 * nx_faces, 4)
+    np.testing.assert_allclose(targ[:nx_faces], np.broadcast_to(D, (nx_faces, 4)), atol=1e-12)
+    np.testing.assert_allclose(targ[nx_faces:], np.broadcast_to(D[[0, 2, 1, 3]], (nx_faces, 4)),
+                               atol=1e-12)
+    # row-major face order: x face (row 2, column 3) and y face (row 4, column 1)
+    _, _, fx, _ = L.face_data(qc, 0, "periodic")
+    _, _, fy, _ = L.face_data(qc, 1, "periodic")
+    np.testing.assert_array_equal(feats[2 * 7 + 3], fx[:, 2, 3])
+    np.testing.assert_array_equal(feats[nx_faces + 4 * 6 + 1], fy[:, 4, 1])
+
+
+def test_axis_swap_gives_identical_features():
+    """Transposing the grid and swapping j_x with j_y turns x faces into y
+    faces with the same 16 features and indicator (the face frame makes the
+    features axis-free)."""
+    q = _random_grid(7, 42)
+    qt = q[[0, 2, 1, 3]].transpose(0, 2, 1).copy()
+    for bc in ("periodic", "transmissive"):
+        _, _, fx, ix = L.face_data(q, 0, bc)
+        _, _, fy, iy = L.face_data(qt, 1, bc)
+        np.testing.assert_array_equal(fy, fx.transpose(0, 2, 1))
+        np.testing.assert_array_equal(iy, ix.T)
