@@ -91,13 +91,16 @@ __device__ __forceinline__ Prim<T> decode(const T (&q)[D + 2], T gamma) {
   return w;
 }
 
-// max_j (|u_j| + c) of one volume (patch maxima and the CFL condition).
+// max_j (|u_j| + c) of one volume (patch maxima and the CFL condition), as
+// max_j |j_j| * |1/rho| + c: |u_j| = |j_j| |1/rho| holds for either sign of
+// rho, so a state with rho < 0 (and p < 0, where c is real) still gives a
+// non-negative speed, as eq. (5) does.
 template <typename T, int D>
 __device__ __forceinline__ T max_wave_speed(const T (&q)[D + 2], const Prim<T>& w) {
   T m = fabs(q[1]);
 #pragma unroll
   for (int k = 1; k < D; ++k) m = nanmax_pos(m, T(fabs(q[1 + k])));
-  return fma(m, w.ir, w.c);
+  return fma(m, T(fabs(w.ir)), w.c);
 }
 
 // Rusanov flux across a face normal to axis K between left state L and right

@@ -333,6 +333,36 @@ def test_fused_step_nan_gives_nan_dt():
     assert (st.workspace.cpu().numpy() == 0).all()
 
 
+def test_negative_density_and_pressure_give_the_oracle_wave_speed():
+    """A volume with rho < 0 and p < 0 (c = sqrt(gamma p / rho) is real there)
+    has |u_j| + c >= 0 as in eq. (5): the per-patch maxima of fv_max_eigenvalue
+    equal the oracle's, and the fused step's time step is non-negative or NaN,
+    never negative."""
+    import torch
+    _say("[rho < 0, p < 0 volume: wave speed and dt]")
+    grid, q = W.grid_3d_random_smooth(2, 8, seed=23)
+    bad = q.copy()
+    bad[:, 2, 5, 6] = [-0.5, 3.0, -0.2, 0.1, -10.0]  # p = 0.4 (-10 + 9.05) < 0, |u_x| = 6
+    flat_h = grid.pack(bad)
+    per_ref, glob_ref = oracle.max_eigenvalue(grid.offsets(), flat_h, 3, 8, True)
+    assert np.isfinite(per_ref).all() and (per_ref > 0).all()
+    pd = fv.upload_patches(grid.descriptors())
+    per = torch.full((grid.n,), -1.0, dtype=torch.float64, device="cuda")
+    fv.max_eigenvalue(pd, to_dev(flat_h), per, dim=3, p=8)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(per.cpu().numpy(), per_ref, rtol=LAM_TOL, atol=0)
+    st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
+                    grid.pack_compact(bad), dim=3, p=8, mode="fused")
+    assert st.dt.item() > 0.0
+    for _ in range(3):
+        st.step()
+        torch.cuda.synchronize()
+        dt = st.last_dt().item()
+        assert math.isnan(dt) or dt >= 0.0, dt
+        me = st.per_patch.cpu().numpy()
+        assert (np.isnan(me) | (me >= 0.0)).all(), me
+
+
 def test_gather_bad_neighbours_are_flagged():
     import torch
     _say("[gather: bad neighbour entries]")
