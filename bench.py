@@ -194,6 +194,45 @@ def plain_path(grid, q, steps):
             "update_hbm_frac": bpc * grid.cells / (upd_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+class StepGraphs:
+    """``steps`` steps of a ping-pong stepper (update + swap) captured as HIP
+    graphs.  A step swaps the two state (and time-step) buffers, so an odd
+    step count ends in the other buffer than it started: then two graphs are
+    captured, one starting from each buffer, and replays alternate between
+    them, so that every replay continues the run exactly ``steps`` steps
+    further.  ``finish()`` re-aligns the stepper's buffer roles with the data
+    after the replays."""
+
+    def __init__(self, st, steps):
+        import torch
+        self.st, self.steps, self.replays = st, steps, 0
+        self.graphs = []
+        stream = torch.cuda.current_stream()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        for _ in range(1 if steps % 2 == 0 else 2):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(g, stream=side):
+                    for _ in range(steps):
+                        st.update()
+                        st.swap()
+            self.graphs.append(g)
+        stream.wait_stream(side)
+        # capturing an even number of steps in total leaves the stepper's
+        # buffer roles where they were
+
+    def replay(self):
+        self.graphs[self.replays % len(self.graphs)].replay()
+        self.replays += 1
+
+    def finish(self):
+        """After the last replay: the data moved replays * steps steps."""
+        if (self.replays * self.steps) % 2:
+            self.st.swap()
+        self.graphs = []
+
+
 def ramp(graph, seconds):
     """Replay a captured graph, untimed, until `seconds` of wall time have
     passed (at least once), so that the timed replay runs at the sustained
@@ -247,15 +286,7 @@ def fp32_path(grid, q, steps, warmup, ramp_s):
     for _ in range(warmup):
         st.step()
     stream = torch.cuda.current_stream()
-    graph = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream()
-    side.wait_stream(stream)
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(graph, stream=side):
-            for _ in range(steps):
-                st.update()
-                st.swap()
-    stream.wait_stream(side)
+    graph = StepGraphs(st, steps)
     ramp(graph, ramp_s)
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record(stream)
@@ -263,6 +294,7 @@ def fp32_path(grid, q, steps, warmup, ramp_s):
     t1.record(stream)
     torch.cuda.synchronize()
     total = t0.elapsed_time(t1)
+    graph.finish()
     del graph, st
     errs = fp32_vs_fp64(grid, q)
     l2, li = errs[100]
@@ -642,15 +674,7 @@ def main():
     # and once timed with events on the stream that runs it.  The per-launch kernel time is the timed replay
     # divided by K (an upper bound: it includes the gap between graph nodes).
     stream = torch.cuda.current_stream()
-    graph = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream()
-    side.wait_stream(stream)
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(graph, stream=side):
-            for _ in range(args.steps):
-                st.update()
-                st.swap()
-    stream.wait_stream(side)
+    graph = StepGraphs(st, args.steps)
     ramp_replays = ramp(graph, args.ramp_s)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
@@ -660,6 +684,7 @@ def main():
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     upd_ms = np.full(args.steps, total_ms / args.steps)
+    graph.finish()
     del graph
 
     # for comparison: eager launches timed by HIP events that the dispatch
