@@ -43,6 +43,8 @@ def _load():
                                    _i64p, _i64p, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
                                    ctypes.c_int]
     lib.oracle_fv_step.restype = ctypes.c_int
+    lib.oracle_fv_step_alg1.argtypes = lib.oracle_fv_step.argtypes
+    lib.oracle_fv_step_alg1.restype = ctypes.c_int
     lib.oracle_max_eigenvalue.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, _i64p, ctypes.c_int, _dp, _dp, _dp]
     lib.oracle_max_eigenvalue.restype = ctypes.c_int
@@ -100,14 +102,19 @@ def rusanov(left, right, d, direction, gamma=1.4):
 
 
 def fv_step(q_in_off, q_out_off, dx, dt, q_in, d, p, gamma=1.4, *, q_out=None,
-            out_halo=False, out_len=None, nthreads=0):
+            out_halo=False, out_len=None, nthreads=0, order="faces"):
     """One explicit Euler step of every patch (Section 2 eqs. (3)-(5), Algorithm 1).
 
     q_in_off / q_out_off: int64[n] element offsets of each patch block.
     dx: float64[n, 3]; dt: float64[n].
+    order: "faces" (one Rusanov flux difference per face) or "alg1" (the step
+    order of Algorithm 1: copy, dissipative parts, central parts; equal up to
+    rounding).
     Returns (q_out, max_eig[n]).  When q_out is given it is updated in place
     (only the interior volumes of each output block are written).
     """
+    if order not in ("faces", "alg1"):
+        raise ValueError("order must be 'faces' or 'alg1'")
     lib = _load()
     q_in_off, ip = _i64(q_in_off)
     q_out_off, op = _i64(q_out_off)
@@ -124,8 +131,9 @@ def fv_step(q_in_off, q_out_off, dx, dt, q_in, d, p, gamma=1.4, *, q_out=None,
     if q_out.dtype != np.float64 or not q_out.flags.c_contiguous:
         raise ValueError("q_out must be a contiguous float64 array")
     me = np.empty(n)
-    rc = lib.oracle_fv_step(n, d, p, gamma, ip, op, int(bool(out_halo)), dxp, dtp, qip,
-                            q_out.ctypes.data_as(_dp), me.ctypes.data_as(_dp), int(nthreads))
+    fn = lib.oracle_fv_step if order == "faces" else lib.oracle_fv_step_alg1
+    rc = fn(n, d, p, gamma, ip, op, int(bool(out_halo)), dxp, dtp, qip,
+            q_out.ctypes.data_as(_dp), me.ctypes.data_as(_dp), int(nthreads))
     if rc != 0:
         raise ValueError("oracle_fv_step rejected its arguments")
     return q_out, me

@@ -17,9 +17,9 @@
  *     (E_t + p) u is used.  The equation of state is not printed; the ideal
  *     gas law p = (gamma - 1)(E_t - |j|^2 / (2 rho)) is used.
  *   - Update, Section 2, eq. (3): explicit Euler in time, flux difference over
- *     the faces of each volume; in d dimensions the 2d faces are summed
- *     (Algorithm 1, step "update with the fluxes from the 2d adjacent faces,
- *     scaled by dt/dx"), one dx per axis, axes in the order x, y, z.
+ *     the faces of each volume; in d dimensions the fluxes of all 2d faces
+ *     of a volume enter its update, each difference scaled by dt/dx
+ *     (Algorithm 1, step 7), one dx per axis, axes in the order x, y, z.
  *   - Rusanov flux, Section 2, eq. (4): F = 1/2 [f(L) + f(R) - a (R - L)].
  *   - Wave speed, Section 2, eq. (5): a = max |lambda_k|; read as the larger of
  *     the two one-sided directional values |u_j| + c (the sup over the state
@@ -195,6 +195,109 @@ int oracle_fv_step(int64_t n, int d, int p, double gamma,
           first = 0;
         }
     if (max_eig) max_eig[b] = lam;
+  }
+  return 0;
+}
+
+/*
+ * The same step evaluated in the step order of Algorithm 1 instead of one
+ * flux difference per face (reading of its garbled steps 2-7: the Rusanov
+ * flux of eq. (4) split into its dissipative and central parts, each scaled
+ * by dt/dx).  For every patch:
+ *   step 1      Q_new = Q_old on the interior;
+ *   steps 2-4   for each axis j: a at the low and high face of each volume
+ *               (eq. (5) on the two adjacent old states) and the dissipative
+ *               part D = -1/2 a (Q_R - Q_L) of both face fluxes;
+ *               Q_new -= dt/dx_j (D(i+1/2) - D(i-1/2));
+ *   steps 5-7   for each axis j: the central part C = 1/2 (f^j(Q_L) + f^j(Q_R))
+ *               of both face fluxes; Q_new -= dt/dx_j (C(i+1/2) - C(i-1/2));
+ *   step 8      non-conservative product: zero for the Euler equations;
+ *   step 10     per-patch maximum eigenvalue of Q_new.
+ * D + C is the face flux of eq. (4), so the result equals oracle_fv_step's
+ * up to rounding.  Arguments and return value as for oracle_fv_step.
+ */
+int oracle_fv_step_alg1(int64_t n, int d, int p, double gamma,
+                        const int64_t* in_off, const int64_t* out_off, int out_halo,
+                        const double* dx, const double* dt,
+                        const double* q_in, double* q_out, double* max_eig,
+                        int nthreads) {
+  if ((d != 2 && d != 3) || p < 1 || n < 0) return -1;
+  int s = d + 2;
+  int w = p + 2;
+  int wo = out_halo ? p + 2 : p;
+  int o = out_halo ? 1 : 0;
+  int pz = (d == 3) ? p : 1;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+  for (int64_t b = 0; b < n; ++b) {
+    const double* in = q_in + in_off[b];
+    double* out = q_out + out_off[b];
+    /* step 1: copy */
+    for (int z = 0; z < pz; ++z)
+      for (int y = 0; y < p; ++y)
+        for (int x = 0; x < p; ++x) {
+          int zc = (d == 3) ? z + 1 : 0;
+          double qc[OR_MAXS];
+          or_get(in, d, w, x + 1, y + 1, zc, qc);
+          or_put(out, d, wo, x + o, y + o, (d == 3) ? z + o : 0, qc);
+        }
+    /* steps 2-4 (part = 0, dissipative), then steps 5-7 (part = 1, central) */
+    for (int part = 0; part < 2; ++part)
+      for (int z = 0; z < pz; ++z)
+        for (int y = 0; y < p; ++y)
+          for (int x = 0; x < p; ++x) {
+            int zc = (d == 3) ? z + 1 : 0;
+            int zo = (d == 3) ? z + o : 0;
+            double qc[OR_MAXS], qn[OR_MAXS];
+            or_get(in, d, w, x + 1, y + 1, zc, qc);
+            or_get(out, d, wo, x + o, y + o, zo, qn);
+            for (int j = 0; j < d; ++j) {
+              int ex = (j == 0), ey = (j == 1), ez = (j == 2);
+              double qm[OR_MAXS], qp[OR_MAXS], Fm[OR_MAXS], Fp[OR_MAXS];
+              or_get(in, d, w, x + 1 - ex, y + 1 - ey, zc - ez, qm);
+              or_get(in, d, w, x + 1 + ex, y + 1 + ey, zc + ez, qp);
+              if (part == 0) {
+                double am = or_nanmax(oracle_eigenvalue(qm, d, j, gamma),
+                                      oracle_eigenvalue(qc, d, j, gamma));
+                double ap = or_nanmax(oracle_eigenvalue(qc, d, j, gamma),
+                                      oracle_eigenvalue(qp, d, j, gamma));
+                for (int k = 0; k < s; ++k) {
+                  Fm[k] = -0.5 * am * (qc[k] - qm[k]);
+                  Fp[k] = -0.5 * ap * (qp[k] - qc[k]);
+                }
+              } else {
+                double fm[OR_MAXS], fc[OR_MAXS], fp[OR_MAXS];
+                oracle_flux(qm, d, j, gamma, fm);
+                oracle_flux(qc, d, j, gamma, fc);
+                oracle_flux(qp, d, j, gamma, fp);
+                for (int k = 0; k < s; ++k) {
+                  Fm[k] = 0.5 * (fm[k] + fc[k]);
+                  Fp[k] = 0.5 * (fc[k] + fp[k]);
+                }
+              }
+              double r = dt[b] / dx[3 * b + j];
+              for (int k = 0; k < s; ++k) qn[k] = qn[k] - r * (Fp[k] - Fm[k]);
+            }
+            or_put(out, d, wo, x + o, y + o, zo, qn);
+          }
+    /* step 8: the non-conservative product of the Euler equations is zero;
+     * step 10: maximum eigenvalue of the new state */
+    if (max_eig) {
+      double lam = 0.0;
+      int first = 1;
+      for (int z = 0; z < pz; ++z)
+        for (int y = 0; y < p; ++y)
+          for (int x = 0; x < p; ++x) {
+            double qn[OR_MAXS];
+            or_get(out, d, wo, x + o, y + o, (d == 3) ? z + o : 0, qn);
+            double l = oracle_max_eigenvalue_state(qn, d, gamma);
+            lam = first ? l : or_nanmax(lam, l);
+            first = 0;
+          }
+      max_eig[b] = lam;
+    }
   }
   return 0;
 }
