@@ -1,0 +1,483 @@
+"""CPU model of the per-lane addressing of the update kernels.
+
+The plane-marching update (every instance of fv_update_kernel, the mixed-size
+persistent kernel's 256-thread bodies) and the learned-correction update
+compute their global and LDS addresses from the thread index, the patch
+geometry and the neighbour table.  This file restates that index arithmetic
+for every thread of a workgroup and checks, on the CPU, that
+
+  * every global load of an active lane falls inside a block the lane may
+    read (its own input block, or a face neighbour's block in the gather
+    form), and every store inside its own output block, interior only;
+  * every LDS index lies inside the lane's own part of the workgroup's LDS
+    (its chunk's slot), and the slots of a workgroup do not overlap;
+  * the halo cells read from LDS are exactly those the load phase wrote,
+    and every face flux read was written;
+  * the values each lane loads are the ones the scheme needs (the own
+    column, the face-halo ring of each plane, the facing neighbour layer).
+
+It is a model: it does not run the kernels, it re-derives their addresses
+from the same layout rules, so a kernel edit that changes its indexing must
+be mirrored here.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+
+def ceil_div(a, b):
+    return -(-a // b)
+
+
+def zsplit(d, p):
+    """Chunks along the marching axis of the single-size kernels."""
+    return {(3, 8): 1, (2, 16): 4, (2, 17): 3, (2, 32): 2}.get((d, p), 1)
+
+
+class Geo:
+    """Patch geometry and thread layout of one update instance."""
+
+    def __init__(self, d, p, ntw=64, zs=None):
+        self.d, self.p, self.ntw = d, p, ntw
+        self.zs = zsplit(d, p) if zs is None else zs
+        self.s = d + 2
+        self.w = p + 2
+        self.vin = self.w ** d
+        self.vout = p ** d
+        self.sm = self.w ** (d - 1)
+        self.smo = p ** (d - 1)
+        self.lanes = p ** (d - 1)
+        self.pc = ceil_div(p, self.zs)
+        self.tpp = self.zs * self.lanes
+        self.ppw = 1 if self.tpp >= ntw else ntw // self.tpp
+        self.nt = ceil_div(self.ppw * self.tpp, 64) * 64
+        self.ring = 4 * p if d == 3 else 2
+        self.nextra = 2 * p if d == 3 else 1
+        self.ncell = self.lanes + self.ring
+        self.nv = self.s + 3
+        self.nf = self.lanes + (p if d == 3 else 1)
+        self.cellbuf = self.nv * self.ncell
+        self.facebuf = (d - 1) * self.s * self.nf
+        self.slot = max(self.cellbuf, self.facebuf)
+        self.nred = max(self.nt // 64, self.ppw * self.zs)
+        self.uneven = p % self.zs != 0
+        # the kernels' static_asserts
+        assert self.ring <= self.lanes
+        assert self.zs == 1 or self.lanes == 64 or self.zs * self.lanes <= 64
+        assert p % self.zs == 0 or self.zs * self.lanes <= 64
+        assert (self.zs - 1) * self.pc < p
+        assert self.nextra <= self.lanes
+        assert self.ppw * self.tpp <= self.nt
+
+
+SINGLE = [(2, 4), (2, 8), (2, 16), (2, 17), (2, 32), (3, 4), (3, 8), (3, 16)]
+MIXED = [(3, 4), (3, 8), (3, 16)]
+
+
+def lds_elements_single(g):
+    return g.ppw * g.zs * g.slot
+
+
+def lds_elements_mixed():
+    return max(Geo(3, p, 256, 1).ppw * Geo(3, p, 256, 1).slot for p in (4, 8, 16))
+
+
+class Block:
+    """A block of one patch: (patch id, kind) where kind is 'in' or 'out'."""
+
+
+def thread_accesses(g, gather, out_halo, nb_present):
+    """Every access of every thread of one workgroup whose slots all hold
+    patches.  Patch slot k is patch k; its face neighbours are patches
+    100 + 2d*k + f when nb_present[f] (gather form), else the face is
+    transmissive.  Returns a list of records
+      (tid, kind, block, index)   kind 'ld' / 'st' / 'lds_w' / 'lds_r' / 'red_w' / 'red_r'
+    with block = (patch, 'in' | 'out') and index the element index inside
+    that block, or block None and index the element index into the
+    workgroup's LDS (or reduction) array."""
+    d, p, s = g.d, g.p, g.s
+    K = d - 1
+    CS = g.vout if gather else g.vin
+    PS = g.smo if gather else g.sm
+    rec = []
+    for tid in range(g.nt):
+        slot = 0 if g.ppw == 1 else tid // g.tpp
+        tp = tid if g.ppw == 1 else tid - slot * g.tpp
+        chunk = 0 if g.zs == 1 else tp // g.lanes
+        l = tp if g.zs == 1 else tp - chunk * g.lanes
+        p0 = chunk * g.pc
+        nrows = min(p - p0, g.pc) if g.uneven else g.pc
+        in_patch = g.ppw * g.tpp == g.nt or tid < g.ppw * g.tpp
+        in_range = in_patch and (g.ppw == 1 or slot < g.ppw)
+        act = in_range  # every descriptor valid
+        x = l % p
+        y = l // p if d == 3 else 0
+        has_ring = l < g.ring
+        q4 = l // p if d == 3 else l
+        rr = l - q4 * p if d == 3 else 0
+        if not act:
+            continue
+        own = (slot, "in")
+        # neighbour blocks of the gather form: face order -x, +x, -y, +y, -z, +z
+        nbk = [(100 + 2 * d * slot + f, "in") if nb_present[f] else None for f in range(2 * d)]
+        col_c = x + (y * p if d == 3 else 0)
+        col_h = (x + 1) + ((y + 1) * g.w if d == 3 else 0)
+        if d == 3:
+            ring_h = [(rr + 1) * g.w, (p + 1) + (rr + 1) * g.w, rr + 1,
+                      (rr + 1) + (p + 1) * g.w][q4] if q4 < 4 else (rr + 1) + (p + 1) * g.w
+        else:
+            ring_h = 0 if l == 0 else p + 1
+        col_in = col_c if gather else col_h
+        jin = p0 if gather else p0 + 1
+        # (block, element index) of the first unknown of each source column
+        gin = (own, col_in + jin * PS)
+        last = (p - 1) * g.smo
+        fl, fh = 2 * K, 2 * K + 1
+        if gather and chunk == 0:
+            glo = (nbk[fl], last + col_c) if nbk[fl] else (own, col_c)
+        else:
+            glo = (own, gin[1] - PS)
+        if gather and chunk == g.zs - 1:
+            ghi = (nbk[fh], col_c) if nbk[fh] else (own, last + col_c)
+        else:
+            ghi = (own, gin[1] + nrows * PS)
+        if gather:
+            if has_ring:
+                hasnb = nbk[q4] is not None
+                if d == 3:
+                    idx = [(p - 1 if hasnb else 0) + p * rr, (0 if hasnb else p - 1) + p * rr,
+                           rr + p * (p - 1 if hasnb else 0), rr + p * (0 if hasnb else p - 1)][q4]
+                else:
+                    idx = (p - 1 if hasnb else 0) if q4 == 0 else (0 if hasnb else p - 1)
+                gring = (nbk[q4] if hasnb else own, idx + p0 * PS)
+            else:
+                gring = (own, col_c + p0 * PS)
+        else:
+            gring = (own, ring_h + PS + p0 * PS)
+
+        def ld_own(j, m):
+            if j == 0:
+                return (glo[0], glo[1] + m * CS)
+            if j == nrows + 1:
+                return (ghi[0], ghi[1] + m * CS)
+            return (own, gin[1] + m * CS + (j - 1) * PS)
+
+        def ld_ring(j, m):
+            return (gring[0], gring[1] + m * CS + (j - 1) * PS)
+
+        for m in range(s):
+            rec.append((tid, "ld", *ld_own(0, m)))
+            rec.append((tid, "ld", *ld_own(1, m)))
+            rec.append((tid, "ld", *ld_ring(1, m)))
+        cell = (slot * g.zs + chunk) * g.slot
+        col_out = col_h + g.sm if out_halo else col_c
+        ostride = g.sm if out_halo else g.smo
+        ocomp = g.vin if out_halo else g.vout
+        fx_lo = l
+        fx_hi = l + 1 if x < p - 1 else g.lanes + (y if d == 3 else 0)
+        fy_lo = l
+        fy_hi = l + p
+        for pl in range(g.pc):
+            live = not g.uneven or pl < nrows
+            if not live:
+                continue
+            if pl + 1 < nrows:
+                for m in range(s):
+                    rec.append((tid, "ld", *ld_ring(pl + 2, m)))
+            for m in range(s):
+                rec.append((tid, "ld", *ld_own(pl + 2, m)))
+            # A
+            for m in range(g.nv):
+                rec.append((tid, "lds_w", None, cell + m * g.ncell + l))
+                if has_ring:
+                    rec.append((tid, "lds_w", None, cell + m * g.ncell + g.lanes + l))
+            # B
+            if l < g.nextra:
+                ydir = d == 3 and l >= p
+                t = l - p if ydir else l
+                if d == 3:
+                    lc = (p - 1) * p + t if ydir else t * p + (p - 1)
+                    rc = g.lanes + 3 * p + t if ydir else g.lanes + p + t
+                else:
+                    lc, rc = p - 1, g.lanes + 1
+                for m in range(g.nv):
+                    rec.append((tid, "lds_r", None, cell + m * g.ncell + lc))
+                    rec.append((tid, "lds_r", None, cell + m * g.ncell + rc))
+            nb = l - 1 if x > 0 else g.lanes + (y if d == 3 else 0)
+            for m in range(g.nv):
+                rec.append((tid, "lds_r", None, cell + m * g.ncell + nb))
+            if d == 3:
+                nb = l - p if y > 0 else g.lanes + 2 * p + x
+                for m in range(g.nv):
+                    rec.append((tid, "lds_r", None, cell + m * g.ncell + nb))
+            # C
+            for m in range(s):
+                rec.append((tid, "lds_wf", None, cell + m * g.nf + fx_lo))
+                if d == 3:
+                    rec.append((tid, "lds_wf", None, cell + (s + m) * g.nf + fy_lo))
+            if l < g.nextra:
+                ydir = d == 3 and l >= p
+                t = l - p if ydir else l
+                base = s * g.nf + p * p + t if ydir else g.lanes + t
+                for m in range(s):
+                    rec.append((tid, "lds_wf", None, cell + base + m * g.nf))
+            # D
+            for m in range(s):
+                rec.append((tid, "lds_rf", None, cell + m * g.nf + fx_hi))
+                rec.append((tid, "lds_rf", None, cell + m * g.nf + fx_lo))
+                if d == 3:
+                    rec.append((tid, "lds_rf", None, cell + (s + m) * g.nf + fy_hi))
+                    rec.append((tid, "lds_rf", None, cell + (s + m) * g.nf + fy_lo))
+                rec.append((tid, "st", (slot, "out"),
+                            col_out + (p0 * ostride) + m * ocomp + pl * ostride))
+        # per-patch maximum
+        pow2 = (g.lanes & (g.lanes - 1)) == 0
+        if pow2:
+            if g.lanes > 64:
+                if (tid & 63) == 0:
+                    rec.append((tid, "red_w", None, tid >> 6))
+                if tid == 0:
+                    for wv in range(1, g.lanes // 64):
+                        rec.append((tid, "red_r", None, wv))
+            elif g.zs > 1:
+                if l == 0:
+                    rec.append((tid, "red_w", None, slot * g.zs + chunk))
+                if l == 0 and chunk == 0:
+                    for c in range(1, g.zs):
+                        rec.append((tid, "red_r", None, slot * g.zs + c))
+        else:
+            rec.append((tid, "lds_max_w", None, tid if tid < g.ppw * g.slot else 0))
+            if l == 0 and chunk == 0:
+                for i in range(1, g.tpp):
+                    rec.append((tid, "lds_max_r", None, slot * g.tpp + i))
+    return rec
+
+
+def _instances():
+    for (d, p), gather, out_halo in itertools.product(SINGLE, (False, True), (False, True)):
+        yield Geo(d, p), lds_elements_single(Geo(d, p)), gather, out_halo, "single"
+    for d, p in MIXED:
+        yield Geo(d, p, 256, 1), lds_elements_mixed(), True, False, "mixed"
+
+
+def _nb_cases(g, gather):
+    if not gather:
+        return [(True,) * (2 * g.d)]
+    return [(True,) * (2 * g.d), (False,) * (2 * g.d),
+            tuple(f % 2 == 0 for f in range(2 * g.d)), tuple(f % 3 == 1 for f in range(2 * g.d))]
+
+
+@pytest.mark.parametrize("g,lds_total,gather,out_halo,kind",
+                         list(_instances()),
+                         ids=lambda v: (f"d{v.d}p{v.p}nt{v.ntw}" if isinstance(v, Geo) else str(v)))
+def test_update_lane_addresses_stay_in_their_blocks(g, lds_total, gather, out_halo, kind):
+    d, p, s = g.d, g.p, g.s
+    blk_in = s * (g.vout if gather else g.vin)
+    blk_out = s * (g.vin if out_halo else g.vout)
+    for nbp in _nb_cases(g, gather):
+        rec = thread_accesses(g, gather, out_halo, nbp)
+        stores = {}
+        for tid, kindr, blk, idx in rec:
+            slot = 0 if g.ppw == 1 else tid // g.tpp
+            chunk = 0 if g.zs == 1 else (tid - slot * g.tpp) // g.lanes
+            if kindr == "ld":
+                assert blk is not None
+                pid, role = blk
+                assert role == "in"
+                # own block, or a face neighbour of this thread's patch
+                assert pid == slot or 100 + 2 * d * slot <= pid < 100 + 2 * d * (slot + 1), \
+                    (tid, blk)
+                assert 0 <= idx < blk_in, (tid, blk, idx)
+            elif kindr == "st":
+                pid, role = blk
+                assert pid == slot and role == "out"
+                assert 0 <= idx < blk_out, (tid, idx)
+                stores.setdefault(pid, []).append(idx)
+            elif kindr in ("lds_w", "lds_r"):
+                lo = (slot * g.zs + chunk) * g.slot
+                assert lo <= idx < lo + g.cellbuf, (tid, kindr, idx)
+                assert idx < lds_total
+            elif kindr in ("lds_wf", "lds_rf"):
+                lo = (slot * g.zs + chunk) * g.slot
+                assert lo <= idx < lo + g.facebuf, (tid, kindr, idx)
+                assert idx < lds_total
+            elif kindr in ("red_w", "red_r"):
+                assert 0 <= idx < g.nred, (tid, kindr, idx)
+            elif kindr in ("lds_max_w", "lds_max_r"):
+                assert 0 <= idx < lds_total, (tid, kindr, idx)
+            else:
+                raise AssertionError(kindr)
+        # every interior volume of every output block is stored exactly once
+        # per unknown, and nothing else
+        for pid in range(g.ppw):
+            got = np.sort(np.array(stores[pid]))
+            want = []
+            for m in range(s):
+                for z in range(p if d == 3 else 1):
+                    for y in range(p):
+                        for x in range(p):
+                            if out_halo:
+                                i = (x + 1) + g.w * (y + 1) + (g.w * g.w * (z + 1) if d == 3 else 0)
+                                want.append(m * g.vin + i)
+                            else:
+                                want.append(m * g.vout + x + p * y + p * p * z)
+            np.testing.assert_array_equal(got, np.sort(np.array(want)))
+
+
+def _column_coords(g, idx, gather):
+    """Coordinates (x, y[, z]) of an element index inside a block (unknown
+    stripped), halo'd when not gather."""
+    v = g.vout if gather else g.vin
+    w = g.p if gather else g.w
+    i = idx % v
+    c = []
+    for _ in range(g.d):
+        c.append(i % w)
+        i //= w
+    return tuple(c)
+
+
+@pytest.mark.parametrize("d,p", SINGLE)
+@pytest.mark.parametrize("gather", [False, True])
+def test_update_loads_read_the_stencil(d, p, gather):
+    """The volumes a patch loads are its interior and exactly its 2d face-halo
+    layers (halo form: the block's own halo; gather form: the facing layer of
+    each neighbour, or the own boundary layer at a transmissive face), never
+    an edge or corner."""
+    g = Geo(d, p)
+    for nbp in _nb_cases(g, gather):
+        rec = thread_accesses(g, gather, False, nbp)
+        seen = set()
+        for tid, kindr, blk, idx in rec:
+            if kindr != "ld":
+                continue
+            slot = 0 if g.ppw == 1 else tid // g.tpp
+            if slot != 0:
+                continue
+            c = _column_coords(g, idx, gather)
+            pid = blk[0]
+            if pid == 0:
+                if gather:
+                    seen.add(("own",) + c)
+                else:
+                    seen.add(("halo",) + tuple(ci - 1 for ci in c))
+            else:
+                f = pid - 100
+                seen.add(("nb", f) + c)
+        # expected set, in patch-interior coordinates (-1 .. p on each axis)
+        want = set()
+        for c in itertools.product(range(p), repeat=d):
+            want.add(("own",) + c if gather else ("halo",) + c)
+        for f in range(2 * d):
+            ax, side = divmod(f, 2)
+            for t in itertools.product(range(p), repeat=d - 1):
+                tl = list(t)
+                c = tl[:ax] + [(-1 if side == 0 else p)] + tl[ax:]
+                if not gather:
+                    want.add(("halo",) + tuple(c))
+                elif nbp[f]:
+                    # the facing layer of the neighbour
+                    c2 = list(c)
+                    c2[ax] = p - 1 if side == 0 else 0
+                    want.add(("nb", 2 * d * 0 + f) + tuple(c2))
+                else:
+                    c2 = list(c)
+                    c2[ax] = 0 if side == 0 else p - 1
+                    want.add(("own",) + tuple(c2))
+        assert seen == want, (sorted(seen - want)[:5], sorted(want - seen)[:5])
+
+
+def test_workgroup_lds_fits_and_slots_are_disjoint():
+    """Each chunk's slot is within the static LDS array and the reduction
+    array holds one entry per chunk or wave; the learned update's LDS layout
+    fits the 160 KB of a CU (64 KB per workgroup as declared)."""
+    for d, p in SINGLE:
+        g = Geo(d, p)
+        assert g.ppw * g.zs * g.slot == lds_elements_single(g)
+        assert g.nred >= g.ppw * g.zs and g.nred >= g.nt // 64
+        assert lds_elements_single(g) * 8 + g.nred * 8 <= 64 * 1024
+    assert lds_elements_mixed() * 8 <= 64 * 1024
+
+
+# ---------------------------------------------------------------------------
+# the learned-correction update (2-D, 16 x 16 patches, two-volume face halo)
+# ---------------------------------------------------------------------------
+LP, LH = 16, 2
+LW = LP + 2 * LH
+NXF = (LP + 1) * LP
+NFACE = 2 * NXF
+
+
+def learned_loaded_cells(nb_present):
+    """LDS cells (y, x) of s.q the load phase writes, and the source (block,
+    y, x) of each: 256 interior threads and 128 halo threads."""
+    cells = {}
+    for tid in range(LP * LP):
+        x, y = tid & 15, tid >> 4
+        cells[(y + LH, x + LH)] = ("own", y, x)
+    for tid in range(128):
+        side, t = tid >> 5, tid & 31
+        layer, pos = t >> 4, t & 15
+        has = nb_present[side]
+        if side == 0:
+            hx, hy, sx, sy = layer, pos + LH, (LP - 2 + layer if has else 0), pos
+        elif side == 1:
+            hx, hy, sx, sy = LP + LH + layer, pos + LH, (layer if has else LP - 1), pos
+        elif side == 2:
+            hx, hy, sx, sy = pos + LH, layer, pos, (LP - 2 + layer if has else 0)
+        else:
+            hx, hy, sx, sy = pos + LH, LP + LH + layer, pos, (layer if has else LP - 1)
+        assert 0 <= sx < LP and 0 <= sy < LP
+        assert (hy, hx) not in cells
+        cells[(hy, hx)] = (("nb", side) if has else "own", sy, sx)
+    return cells
+
+
+@pytest.mark.parametrize("nb_present", [(True,) * 4, (False,) * 4, (True, False, False, True)])
+@pytest.mark.parametrize("nth", [256, 512])
+def test_learned_update_reads_only_loaded_cells_and_written_fluxes(nb_present, nth):
+    cells = learned_loaded_cells(nb_present)
+    # the transmissive halo repeats the boundary volume; a neighbour's halo is
+    # its facing two layers
+    for (hy, hx), (src, sy, sx) in cells.items():
+        iy, ix = hy - LH, hx - LH
+        if 0 <= iy < LP and 0 <= ix < LP:
+            assert (sy, sx) == (iy, ix) and src == "own"
+        elif src == "own":
+            assert (sy, sx) == (min(max(iy, 0), LP - 1), min(max(ix, 0), LP - 1))
+        else:
+            assert (sy, sx) == (iy % LP, ix % LP)
+    fx_w, fy_w = set(), set()
+    waves = nth // 64
+    for wave in range(waves):
+        batch = wave
+        while batch * 64 < NFACE:
+            for l in range(64):
+                f = batch * 64 + l
+                real = f < NFACE
+                ff = f if real else NFACE - 1
+                xdir = ff < NXF
+                gidx = ff if xdir else ff - NXF
+                if xdir:
+                    I, J = gidx % (LP + 1), gidx // (LP + 1)
+                else:
+                    I, J = gidx % LP, gidx // LP
+                for o in range(4):
+                    cx = I - 2 + o + LH if xdir else I + LH
+                    cy = J + LH if xdir else J - 2 + o + LH
+                    assert 0 <= cx < LW and 0 <= cy < LW
+                    assert (cy, cx) in cells, (xdir, I, J, o)
+                if real:
+                    if xdir:
+                        assert 0 <= I <= LP and 0 <= J < LP
+                        fx_w.add((J, I))
+                    else:
+                        assert 0 <= I < LP and 0 <= J <= LP
+                        fy_w.add((J, I))
+            batch += waves
+    # every face written once overall, and the update reads only those
+    assert len(fx_w) == NXF and len(fy_w) == NXF
+    for tid in range(LP * LP):
+        x, y = tid & 15, tid >> 4
+        assert {(y, x), (y, x + 1)} <= fx_w and {(y, x), (y + 1, x)} <= fy_w
