@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# FV_ORACLE_LIB names another build of fv_oracle.c (the sanitizer test loads
+# an AddressSanitizer / UBSan build this way)
+_LIB_PATH = os.environ.get("FV_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
