@@ -63,6 +63,12 @@ def library():
     if not os.path.exists(LIB_PATH):
         raise FVError(FV_EHIP, f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2302_09005_amd.build` (no CPU fallback exists)")
+    # torch's wheel ships its own HIP runtime under the same soname
+    # (libamdhip64.so.7).  Loaded after torch, libfv binds to that copy, so the
+    # process has one HIP runtime and torch's device memory and streams are
+    # valid in libfv's calls.  Loaded before torch, the dynamic linker would
+    # map the system copy as well, and the two runtimes do not share devices.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     lib.fv_last_error.argtypes = []

@@ -272,3 +272,14 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_one_hip_runtime_in_the_process():
+    """libfv binds to the HIP runtime torch loaded (the wheel ships its own
+    copy under the same soname): after fv.library() the process maps exactly
+    one libamdhip64, so torch's device memory and streams are valid in every
+    libfv call whatever was imported first."""
+    fv.library()
+    with open("/proc/self/maps") as f:
+        paths = {line.split()[-1] for line in f if "libamdhip64" in line}
+    assert len(paths) == 1, paths
