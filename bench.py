@@ -309,6 +309,37 @@ def fp32_path(grid, q, steps, warmup, ramp_s):
             "speedup_vs_fp64_step": None}
 
 
+def uneven_fp32_vs_fp64(seed, schedule, checkpoints=(1, 10, 100)):
+    """Relative L2 and Linf differences (worst unknown) between FP32 and FP64
+    runs of the uneven batch from the same initial state, after each number
+    of local steps in checkpoints: {steps: (l2, linf)}.  (The FP64 run matches
+    the oracle to ~1e-14; the tests compare FP32 with the oracle directly.)"""
+    import torch
+    from paper_2302_09005_amd import fv
+    from paper_2302_09005_amd import workloads as W
+    batch, q = W.uneven_batch(20000, seed)
+    sts = [fv.LocalStepper(batch.descriptors(), batch.neighbours(), q, dtype=dt,
+                           schedule=schedule[0], workgroups=schedule[1])
+           for dt in (None, np.float32)]
+    out, done = {}, 0
+    for k in checkpoints:
+        for st in sts:
+            for _ in range(k - done):
+                st.step()
+        done = k
+        torch.cuda.synchronize()
+        r, a = (st.state().double() for st in sts)
+        # unknown-major per patch: gather unknown k of every patch
+        dr = torch.cat([r[o:o + 5 * int(p) ** 3].view(5, -1)
+                        for o, p in zip(batch.offsets(), batch.sizes)], dim=1)
+        da = torch.cat([a[o:o + 5 * int(p) ** 3].view(5, -1)
+                        for o, p in zip(batch.offsets(), batch.sizes)], dim=1)
+        d = da - dr
+        out[k] = (float((d.norm(dim=1) / dr.norm(dim=1)).max()),
+                  float((d.abs().amax(dim=1) / dr.abs().amax(dim=1)).max()))
+    return out
+
+
 def uneven_path(seed, steps=50, dtype=None, tune=True, schedule=("persistent", 0), ramp_s=0.3):
     """The uneven AMR-like batch: 20 000 self-periodic 3-D patches of 4^3, 8^3
     and 16^3 volumes (4:2:1), levels 2-4 (dx = 3^-l / p), local time steps.
@@ -723,8 +754,11 @@ def main():
         uneven_path(args.seed, tune=False, schedule=fixed, ramp_s=args.ramp_s))
     uneven32 = None
     if uneven is not None:
-        uneven32 = uneven_path(args.seed, dtype=np.float32, tune=False,
-                               schedule=tuple(uneven["schedule"]["chosen"]), ramp_s=args.ramp_s)
+        sched = tuple(uneven["schedule"]["chosen"])
+        uneven32 = uneven_path(args.seed, dtype=np.float32, tune=False, schedule=sched,
+                               ramp_s=args.ramp_s)
+        errs = uneven_fp32_vs_fp64(args.seed, sched)
+        uneven32["rel_l2_linf_vs_fp64_by_steps"] = {str(k): list(v) for k, v in errs.items()}
 
     learned_detail = None if args.no_learned else learned_path(args.seed)
     copy_gbs = copy_bandwidth()

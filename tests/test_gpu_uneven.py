@@ -214,7 +214,7 @@ def test_graph_replay_matches_eager():
         assert torch.equal(g_st.per_patch, e_st.per_patch)
 
 
-@pytest.mark.parametrize("steps", [1, 10])
+@pytest.mark.parametrize("steps", [1, 10, 100])
 def test_fp32_uneven_errors(steps):
     batch, q = W.uneven_batch(150, 41)
     ref, _, _, _ = oracle_run(batch, q, steps)
@@ -241,6 +241,38 @@ def test_full_size_batch_sampled_patches():
     np.testing.assert_allclose(dt[pick], dt_ref, rtol=1e-14)
     np.testing.assert_allclose(me[pick], me_ref, rtol=1e-14)
     assert np.isfinite(got).all()
+
+
+def test_fp32_full_size_batch_sampled_patches_at_1_10_100_steps():
+    """The 20 000-patch uneven batch with FP32 state (the benchmarked FP32
+    uneven run), 100 local steps; 64 sampled patches against the FP64 oracle
+    after 1, 10 and 100 steps (self-periodic patches with local time steps
+    evolve independently, so a sample is its own small batch)."""
+    import torch
+    batch, q = W.uneven_batch(20000, 0)
+    st = fv.LocalStepper(batch.descriptors(), batch.neighbours(), q, dtype=np.float32)
+    rng = np.random.default_rng(1)
+    pick = np.sort(rng.choice(batch.n, size=64, replace=False))
+    sub = W.UnevenBatch(batch.sizes[pick], batch.levels[pick])
+    ref = np.concatenate([batch.block(q, b).ravel() for b in pick])
+    dx = np.repeat(sub.dx[:, None], 3, axis=1)
+    dt = t = None
+    done = 0
+    for k in (1, 10, 100):
+        for _ in range(k - done):
+            st.step()
+        torch.cuda.synchronize()
+        got = st.state().cpu().numpy().astype(np.float64)
+        ref, dt, t, _ = oracle.run_local_steps(sub.offsets(), sub.sizes, dx, sub.neighbours(),
+                                               ref, k - done, dt=dt, t=t)
+        done = k
+        gs = np.concatenate([batch.block(got, b).ravel() for b in pick])
+        l2, li = rel_l2_linf(by_unknown(sub, gs), by_unknown(sub, ref))
+        _say(f"[fp32 uneven 20000, 64 sampled vs fp64 oracle] {k} steps: rel L2 {l2:.2e} "
+             f"rel Linf {li:.2e}")
+        assert l2 <= TOL32 and li <= TOL32
+        desc = st.descriptors()
+        np.testing.assert_allclose(desc["t"][pick], t, rtol=1e-5)
 
 
 def test_autotuner_restores_the_run_and_picks_a_candidate():
