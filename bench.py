@@ -71,7 +71,8 @@ def kernel_source_hash():
 
 
 def read_traffic():
-    """HBM bytes per update launch from the committed rocprofv3 counter
+    """L2-to-fabric bytes (FETCH_SIZE + WRITE_SIZE, Infinity Cache hits
+    included) per update launch from the committed rocprofv3 counter
     summary, or None when absent or taken on a different kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -85,7 +86,7 @@ def read_traffic():
     if kv.get("source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["l2_fabric_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -124,36 +125,56 @@ class HipEvents:
             self.lib.hipEventDestroy(h)
 
 
-def cpu_baseline(grid, flat, budget_s, max_steps):
-    """The CPU oracle (unchanged) on a bounded sample of the same workload."""
+def host_cpu_model():
+    """Model name of the host CPU (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(grid, flat, budget_s, max_steps, samples=3):
+    """The CPU oracle (unchanged) on a bounded sample of the same workload:
+    one untimed warm-up step, then `samples` timed samples of whole steps
+    (each within budget_s / samples seconds); the value is their median."""
     import oracle
     off = grid.offsets()
     dx = np.full((grid.n, 3), grid.dx)
     nb = grid.neighbours()
     threads = oracle.num_threads()
     # one untimed step to fault pages in, then whole steps until the budget
-    oracle.run_steps(off, dx, flat, nb, grid.d, grid.p, 1)
-    a = flat.copy()
-    steps = 0
-    t0 = time.perf_counter()
-    while steps < max_steps and time.perf_counter() - t0 < budget_s:
-        a, _, _ = oracle.run_steps(off, dx, a, nb, grid.d, grid.p, 1)
-        steps += 1
-    el = time.perf_counter() - t0
-    # the same oracle on one thread, for scale (a few steps)
-    s1 = 0
-    t1 = time.perf_counter()
-    while s1 < 3 and (s1 == 0 or time.perf_counter() - t1 < budget_s / 4):
+    a, _, _ = oracle.run_steps(off, dx, flat, nb, grid.d, grid.p, 1)
+    rates, descr = [], []
+    per = budget_s / samples
+    for _ in range(samples):
+        steps = 0
+        t0 = time.perf_counter()
+        while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < per):
+            a, _, _ = oracle.run_steps(off, dx, a, nb, grid.d, grid.p, 1)
+            steps += 1
+        el = time.perf_counter() - t0
+        rates.append(grid.cells * steps / el)
+        descr.append(f"{steps} steps in {el:.2f} s")
+    # the same oracle on one thread, for scale: median of 3 single steps
+    one = []
+    for _ in range(3):
+        t1 = time.perf_counter()
         a, _, _ = oracle.run_steps(off, dx, a, nb, grid.d, grid.p, 1, nthreads=1)
-        s1 += 1
-    el1 = time.perf_counter() - t1
-    return {"value": grid.cells * steps / el, "unit": "cell-updates/s", "cores": threads,
+        one.append(grid.cells / (time.perf_counter() - t1))
+    return {"value": float(np.median(rates)), "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} full steps (CFL + update + halo fill) of the 4096x8^3 workload, "
-                      f"seed 0, plain C oracle, OpenMP over patches with {threads} threads, "
-                      f"{el:.1f} s",
-            "single_thread_value": grid.cells * s1 / el1,
-            "single_thread_sample": f"{s1} full steps on 1 thread, {el1:.1f} s"}
+            "sample": f"median of {samples} samples of full steps (CFL + update + halo fill) "
+                      f"of the 4096x8^3 workload, seed 0, after one warm-up step; plain C "
+                      f"oracle, OpenMP over patches with {threads} threads; "
+                      + "; ".join(descr),
+            "samples_cell_updates_per_s": rates,
+            "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count(),
+            "single_thread_value": float(np.median(one)),
+            "single_thread_sample": "median of 3 single full steps on 1 thread"}
 
 
 def plain_path(grid, q, steps):
@@ -307,6 +328,42 @@ def fp32_path(grid, q, steps, warmup, ramp_s):
             "rel_l2_vs_fp64": l2, "rel_linf_vs_fp64": li, "compared_after_steps": 100,
             "rel_l2_linf_vs_fp64_by_steps": {str(k): list(v) for k, v in errs.items()},
             "speedup_vs_fp64_step": None}
+
+
+def out_of_cache_path(q, steps=20, ramp_s=0.3):
+    """The headline's fused FP64 step on 32 768 patches of 8^3: the 4096-patch
+    field tiled 2 x 2 x 2 over a periodic 256^3 grid (dx = 1/256).  The two
+    state buffers (2 x 671 MB) cannot stay in the 256 MB Infinity Cache, so
+    every step streams its state from HBM (the launch writes with streaming
+    stores).  Timed as the headline: eager warm-up, a graph of `steps` steps,
+    untimed replays for ramp_s seconds, one timed replay."""
+    import torch
+    from paper_2302_09005_amd import fv
+    from paper_2302_09005_amd import workloads as W
+    grid = W.PatchGrid(3, 8, (32, 32, 32), 1.0 / 256)
+    st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
+                    grid.pack_compact(np.tile(q, (1, 2, 2, 2))), dim=3, p=8, mode="fused")
+    for _ in range(3):
+        st.step()
+    stream = torch.cuda.current_stream()
+    graph = StepGraphs(st, steps)
+    ramp(graph, ramp_s)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    graph.replay()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1)
+    graph.finish()
+    finite = bool(torch.isfinite(st.state()).all().item())
+    del graph, st
+    bpc = algorithmic_bytes_per_cell(3, 8, 5, 8)
+    us = total * 1e3 / steps
+    return {"patches": grid.n, "steps": steps, "update_us": us,
+            "cell_updates_per_s": grid.cells / (us * 1e-6),
+            "achieved_gbs": bpc * grid.cells / (us * 1e-6) / 1e9,
+            "hbm_frac": bpc * grid.cells / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "state_bytes_per_buffer": grid.cells * 5 * 8, "state_finite": finite}
 
 
 def uneven_fp32_vs_fp64(seed, schedule, checkpoints=(1, 10, 100)):
@@ -760,6 +817,7 @@ def main():
         errs = uneven_fp32_vs_fp64(args.seed, sched)
         uneven32["rel_l2_linf_vs_fp64_by_steps"] = {str(k): list(v) for k, v in errs.items()}
 
+    out_of_cache = out_of_cache_path(q, ramp_s=args.ramp_s)
     learned_detail = None if args.no_learned else learned_path(args.seed)
     copy_gbs = copy_bandwidth()
 
@@ -798,6 +856,7 @@ def main():
                    "eager_dispatch_event_us": eager_dispatch_us,
                    "eager_step_us": eager_step_us,
                    "final_lambda": lam_final, "state_finite": finite,
+                   "out_of_cache_32768": out_of_cache,
                    "plain_halo_path": plain,
                    "fp32_path": f32,
                    "uneven_batch": uneven,

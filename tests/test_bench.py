@@ -38,9 +38,9 @@ def test_traffic_summary_is_consistent():
     kv = _traffic_fields()
     fetch = float(kv["fetch_size_kib_per_dispatch"]) * 1024 * float(kv["fetch_scale"])
     write = float(kv["write_size_kib_per_dispatch"]) * 1024 * float(kv["write_scale"])
-    assert abs(fetch - float(kv["hbm_read_bytes_per_launch"])) <= 1e-3 * fetch
-    assert abs(write - float(kv["hbm_write_bytes_per_launch"])) <= 1e-3 * write
-    total = float(kv["hbm_bytes_per_launch"])
+    assert abs(fetch - float(kv["l2_fabric_read_bytes_per_launch"])) <= 1e-3 * fetch
+    assert abs(write - float(kv["l2_fabric_write_bytes_per_launch"])) <= 1e-3 * write
+    total = float(kv["l2_fabric_bytes_per_launch"])
     assert abs(total - fetch - write) <= 1e-3 * total
     alg = float(kv["algorithmic_bytes_per_launch"])
     assert alg == bench.algorithmic_bytes_per_cell(3, 8, 5, 8) * 4096 * 8 ** 3
@@ -54,7 +54,7 @@ def test_traffic_summary_is_consistent():
 def test_traffic_reported_only_for_the_measured_source(monkeypatch, tmp_path):
     kv = _traffic_fields()
     if kv.get("source_sha256_16") == bench.kernel_source_hash():
-        assert bench.read_traffic() == float(kv["hbm_bytes_per_launch"])
+        assert bench.read_traffic() == float(kv["l2_fabric_bytes_per_launch"])
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.read_traffic() is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
