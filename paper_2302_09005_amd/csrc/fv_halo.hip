@@ -4,6 +4,13 @@
 // patch's own boundary volume.  One thread per halo value; the innermost
 // thread index runs along the first tangential axis, which is contiguous in
 // memory for y- and z-faces.  Edge and corner halo volumes are not touched.
+//
+// The x-face values are strided (one volume per row of p + 2), so every one
+// of them costs a whole memory sector, and a row holds the values that two
+// different patches need (the +x halo of one neighbour, the -x halo of the
+// other).  Workgroups are handed to the XCDs in contiguous ranges, so that
+// the workgroups of neighbouring patches share an L2 and the second reader
+// of a row finds it there.
 #include "fv_internal.hpp"
 
 namespace fvk {
@@ -20,7 +27,11 @@ fill_halo_kernel(const fv_patch* __restrict__ patches, int64_t n,
   constexpr int FACE = ipow(P, D - 1);
   constexpr int64_t VIN = ipow(W, D);
   const int64_t total = n * (2 * D) * S * FACE;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // workgroup w runs on XCD w mod 8: give each XCD a contiguous range
+  const int64_t nwg = gridDim.x, w = blockIdx.x;
+  const int64_t xq = nwg / 8, xr = nwg % 8, xc = w % 8;
+  const int64_t wgi = xc * xq + (xc < xr ? xc : xr) + w / 8;
+  const int64_t i = wgi * blockDim.x + threadIdx.x;
   if (i >= total) return;
   int64_t rest = i;
   const int t1 = (int)(rest % P);
