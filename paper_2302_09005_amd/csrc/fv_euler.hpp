@@ -69,7 +69,12 @@ __device__ __forceinline__ double sqrt_fast(double x) {
   // -0, +0 and +inf (class bits 5, 6 and 9): the iteration would give NaN
   return __builtin_amdgcn_class(x, 0x260) ? x : g;
 }
-__device__ __forceinline__ float sqrt_fast(float x) { return sqrtf(x); }
+// Single precision: the hardware square root alone, within one ulp.  The
+// correctly rounded library routine wraps it in range scaling and a
+// correction step, about 15 more instructions per call (13 % of the float
+// update's instructions).  +-0, +inf and NaN pass through, negative arguments
+// give NaN.
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // What a face needs from one adjacent volume besides its conserved state:
 // 1/rho, pressure and sound speed.  Computing 1/rho once per volume replaces
