@@ -27,10 +27,17 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=
          "-Wno-unused-command-line-argument"]
 
 
+# Per-source flags.  The learned update keeps its matrix-core accumulators in
+# ordinary vector registers: tanh and the bfloat16 packing read every
+# accumulator, and accumulation registers would cost one move per value.
+SOURCE_FLAGS = {"fv_learned_infer.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     objs = [os.path.join(LIBDIR, os.path.splitext(src)[0] + ".o") for src in SOURCES]
-    cmds = [[HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmds = [[HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), *extra, "-c", os.path.join(CSRC, src),
+             "-o", obj]
             for src, obj in zip(SOURCES, objs)]
     if verbose:
         for cmd in cmds:

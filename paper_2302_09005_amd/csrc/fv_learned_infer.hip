@@ -48,12 +48,14 @@ __device__ __forceinline__ bf16x8 to_bf16x8(const float* v) {
 }
 
 // tanh(x) = 1 - 2 / (exp(2x) + 1) from the hardware base-2 exponential and
-// reciprocal (a few ulp of float32 away from the correctly rounded value;
-// the result is rounded to bfloat16 next, 2^-9 relative).  +-inf and large
-// |x| give +-1, NaN stays NaN.
+// reciprocal, the last step one fused multiply-add (a few ulp of float32 away
+// from the correctly rounded value for |tanh x| >= 1/2, a few 1e-8 absolute
+// below; the result is rounded to bfloat16 next, 2^-9 relative).  Five
+// instructions, two of them transcendental.  +-inf and large |x| give +-1,
+// NaN stays NaN.
 __device__ __forceinline__ float tanh_fast(float x) {
   const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 / ln 2
-  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+  return __builtin_fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
 }
 
 // Matrix-core lane layout of the 32 x 32 x 16 product (wave64), lane
