@@ -195,6 +195,32 @@ int fv_step_gather(const fv_patch* patches, int64_t n_patches, const int64_t* ne
 int64_t fv_step_workspace_words(int64_t n_patches, int dim, int p);
 
 /*
+ * fv_step_gather_noalloc -- fv_step_gather for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): the same kernel and results, bit for bit, with the
+ * workspace taken from a buffer inside the library instead of an argument.
+ *
+ * The buffer is a static device array of FV_NOALLOC_SCRATCH_WORDS uint64
+ * words (1 MiB) that every GPU the library runs on holds until the process
+ * ends.  The first call on a device looks up its address there and clears it
+ * with a kernel on `stream`; nothing is allocated, freed or synchronised on
+ * any call.  A batch whose workspace need, fv_step_workspace_words(n_patches,
+ * dim, p), exceeds FV_NOALLOC_SCRATCH_WORDS is refused with FV_EINVAL (e.g.
+ * 3-D 8^3: at most 262 080 patches).  Every call leaves the words it used at
+ * zero again.  All calls on one GPU share the one array: calls that overlap in
+ * time on one GPU (different streams, or different host threads) race and
+ * give wrong time steps; serialise them, or use fv_step_gather with a
+ * workspace per stream.  Arguments and outputs otherwise as for
+ * fv_step_gather (FP64 state).
+ */
+#define FV_NOALLOC_SCRATCH_WORDS 131072
+int fv_step_gather_noalloc(const fv_patch* patches, int64_t n_patches, const int64_t* neighbours,
+                           const double* q_in, int64_t q_in_len, double* q_out, int64_t q_out_len,
+                           int dim, int p, int s, double gamma, double cfl,
+                           const double* dt_dev, double* max_eig, double* dt_next,
+                           double* lambda_out, void* stream);
+
+/*
  * FP32 state (bulk flux and update arithmetic in single precision): the same
  * operations on float blocks.  The time step, the per-patch maxima written to
  * max_eig, Lambda and the CFL reduction stay FP64 (double outputs; the FP32

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "fv_internal.hpp"
@@ -424,6 +425,92 @@ int fv_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours
   return step_gather_impl("fv_step_gather", patches, n, neighbours, q_in, q_in_len, q_out,
                           q_out_len, dim, p, s, gamma, cfl, dt_dev, max_eig, dt_next, lambda_out,
                           workspace, workspace_words, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// fv_step_gather without a workspace argument: the fused CFL tree's slots live
+// in a static device array.  Host code never passes the array's name to a
+// kernel (in host code it names a host-side stand-in); it looks up the array's
+// device address once per device and passes that.
+// ---------------------------------------------------------------------------
+namespace {
+
+static __device__ __align__(256) unsigned long long scratch[FV_NOALLOC_SCRATCH_WORDS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[kMaxDevices] = {};
+
+__global__ void clear_words_kernel(unsigned long long* w, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = 0ull;
+}
+
+// Device address of this device's scratch array; on the first call for the
+// device it is looked up and cleared (a kernel on `st`, ordered before the
+// caller's launch).  nullptr on a HIP error (message in g_err).
+unsigned long long* device_scratch(hipStream_t st) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    fail(FV_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    fail(FV_EHIP, "device index %d out of range", dev);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return g_scratch_ptr[dev];
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    fail(FV_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    return nullptr;
+  }
+  unsigned long long* w = static_cast<unsigned long long*>(ptr);
+  hipLaunchKernelGGL(clear_words_kernel, dim3(64), dim3(256), 0, st, w,
+                     (int64_t)FV_NOALLOC_SCRATCH_WORDS);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    fail(FV_EHIP, "clearing the scratch array: %s", hipGetErrorString(e));
+    return nullptr;
+  }
+  g_scratch_ptr[dev] = w;
+  return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fv_step_gather_noalloc(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                           const double* q_in, int64_t q_in_len, double* q_out,
+                           int64_t q_out_len, int dim, int p, int s, double gamma, double cfl,
+                           const double* dt_dev, double* max_eig, double* dt_next,
+                           double* lambda_out, void* stream) {
+  int rc = check_shape(dim, p, 1, s);
+  if (rc) return rc;
+  if (n < 1) return fail(FV_EINVAL, "n_patches must be >= 1");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  const int64_t need = fvk::step_workspace_words(fvk::update_workgroups(dim, p, n));
+  if (need > FV_NOALLOC_SCRATCH_WORDS)
+    return fail(FV_EINVAL,
+                "fv_step_gather_noalloc: %lld patches need %lld scratch words, the library "
+                "holds %d; use fv_step_gather with a workspace",
+                (long long)n, (long long)need, FV_NOALLOC_SCRATCH_WORDS);
+  // every other argument is checked by the shared path before anything runs
+  if (!patches || !neighbours || !q_in || !q_out || !dt_dev || !dt_next)
+    return fail(FV_EINVAL, "null device pointer");
+  unsigned long long* w = device_scratch((hipStream_t)stream);
+  if (!w) return FV_EHIP;
+  return step_gather_impl("fv_step_gather_noalloc", patches, n, neighbours, q_in, q_in_len,
+                          q_out, q_out_len, dim, p, s, gamma, cfl, dt_dev, max_eig, dt_next,
+                          lambda_out, reinterpret_cast<uint64_t*>(w),
+                          (int64_t)FV_NOALLOC_SCRATCH_WORDS, stream);
 }
 
 int fv_step_gather_f32(const fv_patch* patches, int64_t n, const int64_t* neighbours,

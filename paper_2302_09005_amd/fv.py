@@ -90,6 +90,8 @@ def library():
     lib.fv_step_gather.argtypes = [vp, i64, vp, vp, i64, vp, i64, i32, i32, i32, f64, f64, vp, vp,
                                    vp, vp, vp, i64, vp]
     lib.fv_step_gather.restype = i32
+    lib.fv_step_gather_noalloc.argtypes = lib.fv_step_gather.argtypes[:-3] + [vp]
+    lib.fv_step_gather_noalloc.restype = i32
     lib.fv_step_workspace_words.argtypes = [i64, i32, i32]
     lib.fv_step_workspace_words.restype = i64
     lib.fv_max_eigenvalue.argtypes = [vp, i64, vp, i64, i32, i32, i32, i32, i32, f64, vp, vp, vp]
@@ -289,6 +291,27 @@ def step_gather(patches, neighbours, q_in, q_out, dt, dt_next, workspace, *, dim
               q_out.numel(), dim, p, dim + 2, float(gamma), float(cfl), _ptr(dt), _ptr(max_eig),
               _ptr(dt_next), _ptr(lambda_out), _ptr(workspace), workspace.numel(),
               _stream(stream)))
+
+
+def step_gather_noalloc(patches, neighbours, q_in, q_out, dt, dt_next, *, dim, p, gamma=1.4,
+                        cfl=0.4, max_eig=None, lambda_out=None, stream=None):
+    """fv_step_gather_noalloc: fv_step_gather with the library's own scratch
+    array as workspace (FP64 state; nothing is allocated on any call)."""
+    if _same_state(q_in, q_out) != "":
+        raise TypeError("fv_step_gather_noalloc takes float64 state")
+    _dev_f64(dt, "dt")
+    _dev_f64(dt_next, "dt_next")
+    for t, name in ((max_eig, "max_eig"), (lambda_out, "lambda_out")):
+        if t is not None:
+            _dev_f64(t, name)
+    n = _n_patches(patches)
+    _dev_nbr(neighbours, n, dim)
+    if max_eig is not None and max_eig.numel() < n:
+        raise ValueError("max_eig needs one entry per patch")
+    _check(library().fv_step_gather_noalloc(
+        _ptr(patches), n, _ptr(neighbours), _ptr(q_in), q_in.numel(), _ptr(q_out), q_out.numel(),
+        dim, p, dim + 2, float(gamma), float(cfl), _ptr(dt), _ptr(max_eig), _ptr(dt_next),
+        _ptr(lambda_out), _stream(stream)))
 
 
 def max_eigenvalue(patches, q, per_patch, global_out=None, *, dim, p, gamma=1.4, q_halo=True,

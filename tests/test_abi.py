@@ -153,6 +153,26 @@ def test_step_workspace_size_and_rejection_on_host():
     assert lib.fv_step_gather(*bad, None, 0x5000, 4096, None) == fv.FV_EINVAL
 
 
+def test_step_noalloc_refuses_batches_beyond_its_scratch_on_host():
+    lib = fv.library()
+    # 3-D 8^3: one patch per workgroup, 32 words per 64 workgroups plus 32
+    limit = (131072 // 32 - 1) * 64
+    assert fv.step_workspace_words(limit, 3, 8) == 131072
+    assert fv.step_workspace_words(limit + 1, 3, 8) > 131072
+    args = [0x1000, limit + 1, 0x2000, 0x10000, 1000, 0x100000, 1000, 3, 8, 5, 1.4, 0.4, 0x3000,
+            None, 0x4000, None, None]
+    assert lib.fv_step_gather_noalloc(*args) == fv.FV_EINVAL
+    assert "scratch" in lib.fv_last_error().decode()
+    bad = list(args)
+    bad[1] = 8
+    bad[14] = None  # dt_next is required
+    assert lib.fv_step_gather_noalloc(*bad) == fv.FV_EINVAL
+    bad = list(args)
+    bad[1] = 8
+    bad[9] = 4  # s != d + 2
+    assert lib.fv_step_gather_noalloc(*bad) == fv.FV_EINVAL
+
+
 def test_plan_mixed_sorts_by_size_and_fills_units():
     batch, _ = W.uneven_batch(300, 2)
     desc = batch.descriptors()
