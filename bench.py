@@ -215,6 +215,79 @@ def plain_path(grid, q, steps):
             "update_hbm_frac": bpc * grid.cells / (upd_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def halo_step_path(grid, q, steps, warmup, ramp_s):
+    """The paper's halo'd layout in ONE launch per step (fv_step_halo: update,
+    face-halo exchange pushed into the output halos, next CFL step), timed as
+    the headline (graph of the steps, untimed replays first, one timed
+    replay).  Algorithmic bytes per cell as for fv_batch_update, plus the
+    face-halo values the exchange writes."""
+    import torch
+    from paper_2302_09005_amd import fv
+    st = fv.Stepper(grid.descriptors(), grid.neighbours(), grid.pack(q), dim=grid.d, p=grid.p,
+                    mode="halo_step")
+    for _ in range(warmup):
+        st.step()
+    stream = torch.cuda.current_stream()
+    graph = StepGraphs(st, steps)
+    ramp(graph, ramp_s)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    graph.replay()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1)
+    graph.finish()
+    del graph, st
+    d, p, s = grid.d, grid.p, grid.s
+    bpc = algorithmic_bytes_per_cell(d, p, s, 8)
+    halo_bpc = 2 * d * p ** (d - 1) * s * 8 / p ** d  # face-halo values written
+    us = total * 1e3 / steps
+    return {"steps": steps, "step_us": us, "cell_updates_per_s": grid.cells / (us * 1e-6),
+            "algorithmic_bytes_per_cell": bpc + halo_bpc,
+            "hbm_frac": (bpc + halo_bpc) * grid.cells / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+
+
+def profile_kernels(seed, reps):
+    """Every hot kernel `reps` times on its benchmarked workload, eager, for
+    counter collection under rocprofv3 (the counters are per dispatch): the
+    fused FP64 and FP32 steps and the FP64 one-launch halo'd step on
+    4096 x 8^3; the paper's interface (CFL reduction, halo'd update, halo
+    fill); the learned update on 4096 patches of 16^2 with an untrained
+    network (the same instructions as a trained one)."""
+    import torch
+    from paper_2302_09005_amd import fv
+    from paper_2302_09005_amd import learned
+    from paper_2302_09005_amd import workloads as W
+    grid, q = W.grid_3d_random_smooth(16, 8, seed=seed)
+    for mode, dtype in (("fused", np.float64), ("fused", np.float32), ("halo", np.float64),
+                        ("halo_step", np.float64)):
+        halo = mode.startswith("halo")
+        st = fv.Stepper(grid.descriptors(out_halo=halo, in_halo=halo), grid.neighbours(),
+                        grid.pack(q) if halo else grid.pack_compact(q), dim=3, p=8, mode=mode,
+                        dtype=dtype)
+        for _ in range(reps):
+            st.step()
+        torch.cuda.synchronize()
+        print(f"profiled {mode} {np.dtype(dtype).name}: {reps} steps", flush=True)
+        del st
+    rng = np.random.default_rng(seed)
+    blob = np.zeros(fv.MLP_BLOB_WORDS, np.float32)
+    o = fv.BLOB_OFFSETS
+    for name, fi, fo in (("w1", 16, 64), ("w2", 64, 64), ("w3", 64, 4)):
+        lim = np.sqrt(6.0 / (fi + fo))
+        blob[o[name]:o[name] + fi * fo] = rng.uniform(-lim, lim, fi * fo)
+    blob[o["x_scale"]:o["x_scale"] + 16] = 1.0
+    blob[o["y_scale"]:o["y_scale"] + 4] = 1e-3
+    blob_d = torch.from_numpy(blob).to("cuda")
+    big, qb = W.grid_riemann_2d(4 * learned.COARSE, learned.P, 200 + seed)
+    run = learned.PatchRun(big, qb)
+    dt = run.cfl_dt(learned.CFL)
+    for _ in range(reps):
+        run.step_learned(dt, blob_d)
+    torch.cuda.synchronize()
+    print(f"profiled learned update, {big.n} patches of {learned.P}^2: {reps} steps", flush=True)
+
+
 class StepGraphs:
     """``steps`` steps of a ping-pong stepper (update + swap) captured as HIP
     graphs.  A step swaps the two state (and time-step) buffers, so an odd
@@ -724,6 +797,8 @@ def main():
                     help="seconds of CPU-oracle work for the baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--profile-kernels", type=int, default=0, metavar="REPS",
+                    help="only run every hot kernel REPS times (counter collection)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -738,6 +813,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.profile_kernels:
+        profile_kernels(args.seed, args.profile_kernels)
         return
     if args.sweep_2d_p17:
         sweep_2d_p17(args.seed, [1, 4, 16, 64, 256, 1024, 4096, 16384], 20)
@@ -797,6 +875,7 @@ def main():
 
     # the paper's interface for comparison: halo'd blocks, update + separate halo fill
     plain = plain_path(grid, q, min(args.steps, 20))
+    plain["one_launch_step"] = halo_step_path(grid, q, args.steps, args.warmup, args.ramp_s)
     # FP32 bulk arithmetic on the same workload and step count
     f32 = fp32_path(grid, q, args.steps, args.warmup, args.ramp_s)
     f32["speedup_vs_fp64_step"] = (total_ms / args.steps) / f32["ms_per_step"]

@@ -221,6 +221,38 @@ int fv_step_gather_noalloc(const fv_patch* patches, int64_t n_patches, const int
                            double* lambda_out, void* stream);
 
 /*
+ * fv_step_halo -- one whole explicit step of the paper's layout in ONE launch:
+ * the update of fv_batch_update (input and output blocks both with halo,
+ * [s][(p+2)^d]), the face-halo exchange of the NEW state (what fv_fill_halo
+ * on q_out would do next) and the CFL time step of the next step (as in
+ * fv_step_gather).  The exchange is pushed: when a patch has computed its new
+ * boundary volumes it also stores them into the face halos that read them,
+ * so the next step's input is complete when the launch ends, and no separate
+ * halo pass reads the state again (Section 2: the engine keeps halos
+ * consistent; here it is done while the update writes).
+ *
+ * neighbours  device int64 [n_patches][2*dim], as for fv_fill_halo; the table
+ *             must be mutual: if neighbours[b][f] = a >= 0, then
+ *             neighbours[a][f^1] = b (every conforming patch grid, periodic
+ *             or not, has this property).  -1 = transmissive: the face halo
+ *             repeats the patch's own boundary volume.  A patch with an entry
+ *             that is not mutual, out of range, or names a patch whose
+ *             descriptor fails the check, is not updated, pushes nothing and
+ *             gets NaN in max_eig (so Lambda and dt_next are NaN too).
+ * q_out       blocks [s][(p+2)^d] at patches[b].q_out: interior and face
+ *             halo written, edge and corner halo volumes untouched.
+ * Other arguments (dt_dev, max_eig, dt_next, lambda_out, workspace) as for
+ * fv_step_gather.  Results equal fv_batch_update (q_out_halo = 1), then
+ * fv_fill_halo on q_out, then fv_cfl_timestep, bit for bit.  FP64 state.
+ */
+int fv_step_halo(const fv_patch* patches, int64_t n_patches, const int64_t* neighbours,
+                 const double* q_in, int64_t q_in_len, double* q_out, int64_t q_out_len,
+                 int dim, int p, int halo, int s, double gamma, double cfl,
+                 const double* dt_dev, double* max_eig, double* dt_next,
+                 double* lambda_out, uint64_t* workspace, int64_t workspace_words,
+                 void* stream);
+
+/*
  * FP32 state (bulk flux and update arithmetic in single precision): the same
  * operations on float blocks.  The time step, the per-patch maxima written to
  * max_eig, Lambda and the CFL reduction stay FP64 (double outputs; the FP32

@@ -523,6 +523,35 @@ int fv_step_gather_f32(const fv_patch* patches, int64_t n, const int64_t* neighb
                           workspace, workspace_words, stream);
 }
 
+int fv_step_halo(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                 const double* q_in, int64_t q_in_len, double* q_out, int64_t q_out_len, int dim,
+                 int p, int halo, int s, double gamma, double cfl, const double* dt_dev,
+                 double* max_eig, double* dt_next, double* lambda_out, uint64_t* workspace,
+                 int64_t workspace_words, void* stream) {
+  int rc = check_shape(dim, p, halo, s);
+  if (rc) return rc;
+  if (n < 1) return fail(FV_EINVAL, "n_patches must be >= 1");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (!(cfl > 0.0) || !isfinite(cfl)) return fail(FV_EINVAL, "cfl must be finite and > 0");
+  if (!patches || !neighbours || !q_in || !q_out || !dt_dev || !dt_next || !workspace)
+    return fail(FV_EINVAL, "null device pointer");
+  if (dt_next == dt_dev) return fail(FV_EINVAL, "dt_next must not alias dt_dev");
+  const int64_t need = fvk::step_workspace_words(fvk::update_workgroups(dim, p, n));
+  if (workspace_words < need) return fail(FV_EINVAL, "workspace needs %lld words", (long long)need);
+  if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  if ((rc = overlap_check(q_in, q_in_len, q_out, q_out_len))) return rc;
+  fvk::CflOut co;
+  co.cfl = cfl;
+  co.dt_next = dt_next;
+  co.lambda_out = lambda_out;
+  co.ws = reinterpret_cast<unsigned long long*>(workspace);
+  rc = fvk::launch_step_halo<double>(patches, n, neighbours, q_in, q_in_len, q_out, q_out_len,
+                                     dim, p, gamma, dt_dev, max_eig, co, (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  return launched("fv_step_halo");
+}
+
 int fv_max_eigenvalue(const fv_patch* patches, int64_t n, const double* q, int64_t q_len,
                       int q_halo, int which, int dim, int p, int s, double gamma,
                       double* per_patch, double* global, void* stream) {

@@ -135,6 +135,15 @@ int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighb
                        double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
                        hipStream_t st);
 
+// One whole step of the paper's layout (halo'd input and output blocks): the
+// update, its face-halo exchange pushed into the output halos, and the next
+// CFL step (double state only).
+template <typename T>
+int launch_step_halo(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                     const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int dim, int p,
+                     double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
+                     hipStream_t st);
+
 // Uneven batches (3-D, p in {4, 8, 16}): patches per 256-thread work unit,
 // and one step with local time stepping under the given schedule.
 int mixed_patches_per_unit(int p);

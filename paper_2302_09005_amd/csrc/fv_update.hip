@@ -80,8 +80,15 @@ struct BodyOut {
 // marched in ZS chunks.  b: the patch of this thread's slot (-1: none).
 // lds: PPW * ZS * SLOT elements, red: Geo::NRED elements, both shared.  MODE:
 // see StepMode (kLocalDt needs a writable descriptor array and cfl).  NTS:
-// write the new state with non-temporal stores (the same values).
-template <typename T, int D, int P, int NTW, int ZS, bool GATHER, int MODE, bool NTS>
+// write the new state with non-temporal stores (the same values).  PUSH
+// (halo'd input and output blocks): the halo exchange of the new state is
+// fused into the update, the other way round from GATHER: every boundary
+// volume of the new state is also stored into the face halo that reads it,
+// the facing halo slot of the neighbour's output block (the neighbour must
+// name this patch across the opposite face), or at a transmissive face the
+// adjacent halo slot of the own block.
+template <typename T, int D, int P, int NTW, int ZS, bool GATHER, int MODE, bool NTS,
+          bool PUSH = false>
 __device__ __forceinline__ BodyOut update_body(
     const fv_patch* __restrict__ patches, int64_t n, const int64_t* __restrict__ neighbours,
     const T* __restrict__ qin, int64_t qin_len, T* __restrict__ qout, int64_t qout_len,
@@ -126,6 +133,11 @@ __device__ __forceinline__ BodyOut update_body(
   const int64_t blk_out = out_halo ? (int64_t)S * G::VIN : (int64_t)S * G::VOUT;
   int64_t off_in = 0, off_out = 0;
   int64_t lo_base = 0, hi_base = 0, ring_src = 0;  // element offsets (GATHER)
+  // PUSH: element distance from a boundary volume's own output slot to the
+  // halo slot that receives it, per face (-x, +x, -y, +y[, -z, +z])
+  int64_t pshift[2 * D];
+#pragma unroll
+  for (int f = 0; f < 2 * D; ++f) pshift[f] = 0;
   T r[3] = {T(0), T(0), T(0)};
   double hmin = __builtin_inf();
   double dt_used = 0.0, t_used = 0.0;
@@ -181,6 +193,29 @@ __device__ __forceinline__ BodyOut update_body(
         ring_src = off_in + x + (D == 3 ? y * P : 0);  // own column, never used
       }
     }
+    if constexpr (PUSH) {
+      // halo'd coordinate along the face axis: the boundary volume sits at 1
+      // (low face) or P (high face); it lands at P+1 or 0 of the neighbour's
+      // block, or at 0 or P+1 of the own block (transmissive)
+#pragma unroll
+      for (int f = 0; f < 2 * D; ++f) {
+        const int64_t nb = neighbours[b * 2 * D + f];
+        const int64_t astride = f < 2 ? 1 : f < 4 ? W : (int64_t)W * W;
+        const bool hi = f & 1;
+        if (nb >= 0 && nb < n) {
+          const fv_patch& pn = patches[nb];
+          if (pn.p == P && pn.q_out >= 0 && pn.q_out <= qout_len - blk_out &&
+              neighbours[nb * 2 * D + (f ^ 1)] == b)
+            pshift[f] = (pn.q_out - off_out) + (hi ? -P : P) * astride;
+          else
+            ok = false;
+        } else if (nb == -1) {
+          pshift[f] = hi ? astride : -astride;
+        } else {
+          ok = false;
+        }
+      }
+    }
   }
   if constexpr (G::PPW == 1) {
     // one patch per workgroup: every lane read the same descriptor, so its
@@ -192,6 +227,10 @@ __device__ __forceinline__ BodyOut update_body(
     hi_base = uni(hi_base);
 #pragma unroll
     for (int j = 0; j < 3; ++j) r[j] = uni(r[j]);
+    if constexpr (PUSH) {
+#pragma unroll
+      for (int f = 0; f < 2 * D; ++f) pshift[f] = uni(pshift[f]);
+    }
     hmin = uni(hmin);
     dt_used = uni(dt_used);
     t_used = uni(t_used);
@@ -240,8 +279,8 @@ __device__ __forceinline__ BodyOut update_body(
   auto ld_ring = [&](int j, int m) -> T { return gring[(int64_t)m * CS + (int64_t)(j - 1) * PS]; };
   // NTS: streaming (non-temporal) stores, for outputs too large to stay in
   // the caches until the next step reads them
-  auto st_out = [&](int pl, int m, T v) {
-    T* dst = gout + (int64_t)m * ocomp + (int64_t)pl * ostride;
+  auto st_out = [&](int pl, int m, T v, int64_t shift = 0) {
+    T* dst = gout + (int64_t)m * ocomp + (int64_t)pl * ostride + shift;
     if constexpr (NTS) __builtin_nontemporal_store(v, dst);
     else *dst = v;
   };
@@ -414,6 +453,21 @@ __device__ __forceinline__ BodyOut update_body(
         qn[m] = fma(-r[K], Fhi[m] - Flo[m], v[m]);
         st_out(pl, m, qn[m]);
       }
+      if constexpr (PUSH) {
+        // boundary volumes of the new state into the face halos that read them
+        auto push = [&](int f) {
+#pragma unroll
+          for (int m = 0; m < S; ++m) st_out(pl, m, qn[m], pshift[f]);
+        };
+        if (x == 0) push(0);
+        if (x == P - 1) push(1);
+        if constexpr (D == 3) {
+          if (y == 0) push(2);
+          if (y == P - 1) push(3);
+        }
+        if (p0 + pl == 0) push(2 * K);
+        if (p0 + pl == P - 1) push(2 * K + 1);
+      }
       const Prim<T> wn = decode<T, D>(qn, gamma);
       lam = nanmax_pos(lam, max_wave_speed<T, D>(qn, wn));
 #pragma unroll
@@ -486,7 +540,7 @@ __device__ __forceinline__ int64_t xcd_contiguous(int64_t w, int64_t nwg) {
   return x * q + (x < r ? x : r) + k;
 }
 
-template <typename T, int D, int P, bool GATHER, int MODE, bool NTS>
+template <typename T, int D, int P, bool GATHER, int MODE, bool NTS, bool PUSH>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, Geo<D, P>::NT)))
 fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
                  const int64_t* __restrict__ neighbours,
@@ -507,7 +561,8 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   int64_t b = -1;
   if (slot < G::PPW && i < count) b = order ? order[order_base + i] : i;
   const BodyOut bo =
-      update_body<T, D, P, 64, G::CHUNKS, GATHER, MODE == kLocalDt ? kLocalDt : kPlain, NTS>(
+      update_body<T, D, P, 64, G::CHUNKS, GATHER, MODE == kLocalDt ? kLocalDt : kPlain, NTS,
+                  PUSH>(
       patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo, gamma, dt_dev, max_eig,
       cflo.cfl, b, lds, red);
   const double lam_b = bo.lam;
@@ -645,7 +700,7 @@ fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
 constexpr double kStreamingOutBytes = 128.0 * (1 << 20);
 inline bool streaming_output(double bytes) { return bytes > kStreamingOutBytes; }
 
-template <typename T, int D, int P, bool GATHER, int MODE, bool NTS>
+template <typename T, int D, int P, bool GATHER, int MODE, bool NTS, bool PUSH>
 int launch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin, int64_t qin_len,
            T* qout, int64_t qout_len, int out_halo, T gamma, const double* dt_dev,
            double* max_eig, const CflOut& cflo, const int64_t* order, int64_t order_base,
@@ -657,14 +712,14 @@ int launch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin,
   const LaunchEvents& ev = launch_events();
   // with caller events the dispatch packet itself records them, so they time
   // the kernel's execution and nothing around it
-  hipExtLaunchKernelGGL((fv_update_kernel<T, D, P, GATHER, MODE, NTS>), dim3((unsigned)blocks),
+  hipExtLaunchKernelGGL((fv_update_kernel<T, D, P, GATHER, MODE, NTS, PUSH>), dim3((unsigned)blocks),
                         dim3(G::NT), 0, st, ev.start, ev.stop, 0, patches, n, nbr, qin, qin_len,
                         qout, qout_len, out_halo, gamma, dt_dev, max_eig, cflo, order,
                         order_base, count);
   return 0;
 }
 
-template <typename T, bool GATHER, int MODE>
+template <typename T, bool GATHER, int MODE, bool PUSH = false>
 int dispatch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin,
              int64_t qin_len, T* qout, int64_t qout_len, int out_halo, int dim, int p,
              double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
@@ -672,14 +727,12 @@ int dispatch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qi
   const bool nts = streaming_output((double)count * (dim + 2) * ipow(p, dim) * sizeof(T));
 #define FV_CASE(DD, PP)                                                                        \
   if (dim == DD && p == PP)                                                                    \
-    return nts ? launch<T, DD, PP, GATHER, MODE, true>(patches, n, nbr, qin, qin_len, qout,     \
-                                                       qout_len, out_halo, T(gamma), dt_dev,   \
-                                                       max_eig, cflo, order, order_base,       \
-                                                       count, st)                              \
-               : launch<T, DD, PP, GATHER, MODE, false>(patches, n, nbr, qin, qin_len, qout,    \
-                                                        qout_len, out_halo, T(gamma), dt_dev,  \
-                                                        max_eig, cflo, order, order_base,      \
-                                                        count, st);
+    return nts ? launch<T, DD, PP, GATHER, MODE, true, PUSH>(                                 \
+                     patches, n, nbr, qin, qin_len, qout, qout_len, out_halo, T(gamma), dt_dev, \
+                     max_eig, cflo, order, order_base, count, st)                              \
+               : launch<T, DD, PP, GATHER, MODE, false, PUSH>(                                \
+                     patches, n, nbr, qin, qin_len, qout, qout_len, out_halo, T(gamma), dt_dev, \
+                     max_eig, cflo, order, order_base, count, st);
   FV_CASE(2, 4)
   FV_CASE(2, 8)
   FV_CASE(2, 16)
@@ -742,6 +795,19 @@ int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighb
                                        dim, p, gamma, dt_dev, max_eig, cflo, nullptr, 0, n, st);
 }
 
+template <typename T>
+int launch_step_halo(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                     const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int dim, int p,
+                     double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
+                     hipStream_t st) {
+  return dispatch<T, false, kGlobalCfl, true>(patches, n, neighbours, qin, qin_len, qout,
+                                              qout_len, 1, dim, p, gamma, dt_dev, max_eig, cflo,
+                                              nullptr, 0, n, st);
+}
+template int launch_step_halo<double>(const fv_patch*, int64_t, const int64_t*, const double*,
+                                      int64_t, double*, int64_t, int, int, double,
+                                      const double*, double*, const CflOut&, hipStream_t);
+
 int mixed_patches_per_unit(int p) {
   return p == 16 ? Geo<3, 16, kMixedNT, 1>::PPW
        : p == 8  ? Geo<3, 8, kMixedNT, 1>::PPW
@@ -788,11 +854,11 @@ int launch_step_local(const fv_patch* patches, int64_t n, const int64_t* neighbo
       int rc = FV_EUNSUPPORTED;
 #define FV_CLASS(PP)                                                                          \
   if (plan.class_p[c] == PP)                                                                  \
-    rc = nts ? launch<T, 3, PP, true, kLocalDt, true>(patches, n, neighbours, qin, qin_len,    \
+    rc = nts ? launch<T, 3, PP, true, kLocalDt, true, false>(patches, n, neighbours, qin, qin_len, \
                                                       qout, qout_len, 0, T(gamma), nullptr,   \
                                                       max_eig, co, plan.order, first + k,     \
                                                       per, st)                                \
-             : launch<T, 3, PP, true, kLocalDt, false>(patches, n, neighbours, qin, qin_len,   \
+             : launch<T, 3, PP, true, kLocalDt, false, false>(patches, n, neighbours, qin, qin_len, \
                                                        qout, qout_len, 0, T(gamma), nullptr,  \
                                                        max_eig, co, plan.order, first + k,    \
                                                        per, st);

@@ -90,6 +90,9 @@ def library():
     lib.fv_step_gather.argtypes = [vp, i64, vp, vp, i64, vp, i64, i32, i32, i32, f64, f64, vp, vp,
                                    vp, vp, vp, i64, vp]
     lib.fv_step_gather.restype = i32
+    lib.fv_step_halo.argtypes = [vp, i64, vp, vp, i64, vp, i64, i32, i32, i32, i32, f64, f64, vp,
+                                 vp, vp, vp, vp, i64, vp]
+    lib.fv_step_halo.restype = i32
     lib.fv_step_gather_noalloc.argtypes = lib.fv_step_gather.argtypes[:-3] + [vp]
     lib.fv_step_gather_noalloc.restype = i32
     lib.fv_step_workspace_words.argtypes = [i64, i32, i32]
@@ -291,6 +294,34 @@ def step_gather(patches, neighbours, q_in, q_out, dt, dt_next, workspace, *, dim
               q_out.numel(), dim, p, dim + 2, float(gamma), float(cfl), _ptr(dt), _ptr(max_eig),
               _ptr(dt_next), _ptr(lambda_out), _ptr(workspace), workspace.numel(),
               _stream(stream)))
+
+
+def step_halo(patches, neighbours, q_in, q_out, dt, dt_next, workspace, *, dim, p, gamma=1.4,
+              cfl=0.4, max_eig=None, lambda_out=None, stream=None):
+    """fv_step_halo: the paper's halo'd layout, update + face-halo exchange of
+    the new state (pushed into the output halos) + next CFL step, one launch
+    (float64 state; the neighbour table must be mutual)."""
+    import torch
+    if _same_state(q_in, q_out) != "":
+        raise TypeError("fv_step_halo takes float64 state")
+    _dev_f64(dt, "dt")
+    _dev_f64(dt_next, "dt_next")
+    for t, name in ((max_eig, "max_eig"), (lambda_out, "lambda_out")):
+        if t is not None:
+            _dev_f64(t, name)
+    n = _n_patches(patches)
+    need = step_workspace_words(n, dim, p)
+    if not (workspace.is_cuda and workspace.dtype in (torch.int64, torch.uint64)
+            and workspace.numel() >= need and workspace.is_contiguous()):
+        raise TypeError(f"workspace must be a contiguous 64-bit integer device tensor of "
+                        f">= {need} words")
+    _dev_nbr(neighbours, n, dim)
+    if max_eig is not None and max_eig.numel() < n:
+        raise ValueError("max_eig needs one entry per patch")
+    _check(library().fv_step_halo(
+        _ptr(patches), n, _ptr(neighbours), _ptr(q_in), q_in.numel(), _ptr(q_out), q_out.numel(),
+        dim, p, 1, dim + 2, float(gamma), float(cfl), _ptr(dt), _ptr(max_eig), _ptr(dt_next),
+        _ptr(lambda_out), _ptr(workspace), workspace.numel(), _stream(stream)))
 
 
 def step_gather_noalloc(patches, neighbours, q_in, q_out, dt, dt_next, *, dim, p, gamma=1.4,
@@ -626,7 +657,10 @@ class Stepper:
     the next step's CFL time step).  mode "gather": the same arithmetic as two
     launches, fv_cfl_timestep + fv_batch_update_gather.  mode "halo": blocks
     with halo [s][(p+2)^d]; fv_cfl_timestep + fv_batch_update + fv_fill_halo
-    (the paper's interface, halo kept consistent by a separate pass).  The time
+    (the paper's interface, halo kept consistent by a separate pass).  mode
+    "halo_step": the same blocks and results as "halo" in ONE launch per step
+    (fv_step_halo: the exchange pushed into the output halos, the next CFL
+    step from the fused reduction; float64 state).  The time
     step always comes from the per-patch maxima of the previous step's state;
     nothing leaves the device.  q0 must be laid out for the mode
     (workloads.PatchGrid.pack for "halo", pack_compact otherwise).
@@ -635,14 +669,18 @@ class Stepper:
     def __init__(self, desc, neighbours, q0, *, dim, p, gamma=1.4, cfl=0.4, mode="fused",
                  device="cuda", dtype=None):
         import torch
-        if mode not in ("fused", "gather", "halo"):
-            raise ValueError("mode must be 'fused', 'gather' or 'halo'")
+        if mode not in ("fused", "gather", "halo", "halo_step"):
+            raise ValueError("mode must be 'fused', 'gather', 'halo' or 'halo_step'")
+        if mode == "halo_step" and dtype not in (None, np.float64):
+            raise ValueError("mode 'halo_step' takes float64 state")
         desc = np.ascontiguousarray(desc, dtype=PATCH_DTYPE)
         if not np.array_equal(desc["q_in"], desc["q_out"]):
             raise ValueError("the ping-pong stepper needs q_in == q_out offsets")
         q0 = np.ascontiguousarray(q0, dtype=np.float64 if dtype is None else dtype)
         self.mode = mode
-        self.halo = mode == "halo"
+        self.halo = mode in ("halo", "halo_step")
+        # one launch per step that also computes the next step's dt
+        self.one_launch = mode in ("fused", "halo_step")
         self.dim, self.p, self.gamma, self.cfl = dim, p, gamma, cfl
         self.n = desc.shape[0]
         self.patches = upload_patches(desc, device, dim=dim, p=p, q_out_halo=self.halo,
@@ -660,19 +698,23 @@ class Stepper:
         self._parity = 0
         max_eigenvalue(self.patches, self.a, self.per_patch, dim=dim, p=p, gamma=gamma,
                        q_halo=self.halo)
-        if mode == "fused":
+        if self.one_launch:
             # the first step's dt; later ones come out of the fused launch
             cfl_timestep(self.patches, self.per_patch, dim=dim, cfl=cfl, lambda_out=self.lam,
                          dt_out=self.dt)
 
     def cfl_step(self, stream=None):
-        if self.mode == "fused":
+        if self.one_launch:
             return  # computed by the previous fused launch (or the constructor)
         cfl_timestep(self.patches, self.per_patch, dim=self.dim, cfl=self.cfl,
                      lambda_out=self.lam, dt_out=self.dt, stream=stream)
 
     def update(self, stream=None):
-        if self.mode == "halo":
+        if self.mode == "halo_step":
+            step_halo(self.patches, self.neighbours, self.a, self.b, self.dt, self.dt_next,
+                      self.workspace, dim=self.dim, p=self.p, gamma=self.gamma, cfl=self.cfl,
+                      max_eig=self.per_patch, lambda_out=self.lam, stream=stream)
+        elif self.mode == "halo":
             batch_update(self.patches, self.a, self.b, dim=self.dim, p=self.p, gamma=self.gamma,
                          q_out_halo=True, dt=self.dt, max_eig=self.per_patch, stream=stream)
         elif self.mode == "gather":
@@ -707,7 +749,7 @@ class Stepper:
             _check(self._fn(*self._fused_args[self._parity], _stream(stream)))
 
     def exchange(self, stream=None):
-        if self.halo:
+        if self.mode == "halo":
             fill_halo(self.patches, self.neighbours, self.b, dim=self.dim, p=self.p,
                       stream=stream)
 
@@ -715,7 +757,7 @@ class Stepper:
         """Swap the state buffers (and, fused, the dt buffers): the new state
         becomes the input of the next step."""
         self.a, self.b = self.b, self.a
-        if self.mode == "fused":
+        if self.one_launch:
             self.dt, self.dt_next = self.dt_next, self.dt
             self._parity ^= 1
 
@@ -727,7 +769,7 @@ class Stepper:
 
     def last_dt(self):
         """Device tensor holding the time step used by the most recent step."""
-        return self.dt_next if self.mode == "fused" else self.dt
+        return self.dt_next if self.one_launch else self.dt
 
     def state(self):
         return self.a

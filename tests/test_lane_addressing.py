@@ -481,3 +481,111 @@ def test_learned_update_reads_only_loaded_cells_and_written_fluxes(nb_present, n
     for tid in range(LP * LP):
         x, y = tid & 15, tid >> 4
         assert {(y, x), (y, x + 1)} <= fx_w and {(y, x), (y + 1, x)} <= fy_w
+
+
+def _push_stores(g, counts, bcs):
+    """The PUSH form (halo'd input and output, the new state's boundary
+    volumes also stored into the face halos that read them) on a small patch
+    grid: every push store of every thread of every patch, as
+    (destination element, source patch, unknown, source coords).  Output
+    block b sits at element offset b * s * (p+2)^d.  The pushed shift per
+    face restates the kernel: to the neighbour's block, moved by P along the
+    face axis away from the face (low face) or towards it (high face), or at
+    a transmissive face by one volume out of the own block."""
+    d, p, s, w = g.d, g.p, g.s, g.w
+    K = d - 1
+    npat = int(np.prod(counts))
+    blk = s * g.vin
+    pc_ = np.array(np.unravel_index(np.arange(npat), counts[::-1]))[::-1].T  # (x, y[, z])
+    strides = np.cumprod((1,) + tuple(counts[:-1]))
+
+    def nb(b, f):
+        a, side = f // 2, f % 2
+        c = pc_[b].copy()
+        c[a] += 1 if side else -1
+        if c[a] < 0 or c[a] >= counts[a]:
+            if bcs[a] == "transmissive":
+                return -1
+            c[a] %= counts[a]
+        return int((c * strides).sum())
+
+    out = []
+    for b in range(npat):
+        off_out = b * blk
+        pshift = []
+        for f in range(2 * d):
+            a_str = 1 if f < 2 else (w if f < 4 else w * w)
+            n_ = nb(b, f)
+            hi = f & 1
+            if n_ >= 0:
+                assert nb(n_, f ^ 1) == b  # a grid's table is mutual
+                pshift.append((n_ * blk - off_out) + (-p if hi else p) * a_str)
+            else:
+                pshift.append(a_str if hi else -a_str)
+        for tid in range(g.tpp):
+            chunk = 0 if g.zs == 1 else tid // g.lanes
+            l = tid if g.zs == 1 else tid - chunk * g.lanes
+            p0 = chunk * g.pc
+            nrows = min(p - p0, g.pc) if g.uneven else g.pc
+            x = l % p
+            y = l // p if d == 3 else 0
+            col_h = (x + 1) + ((y + 1) * w if d == 3 else 0)
+            col_out = col_h + g.sm
+            for pl in range(g.pc):
+                if g.uneven and pl >= nrows:
+                    continue
+                zz = p0 + pl
+                src = (x, y, zz) if d == 3 else (x, zz)
+                faces = [f for f in range(2 * K)
+                         if (x if f // 2 == 0 else y) == (p - 1 if f & 1 else 0)]
+                if zz == 0:
+                    faces.append(2 * K)
+                if zz == p - 1:
+                    faces.append(2 * K + 1)
+                for f in faces:
+                    for m in range(s):
+                        dst = off_out + col_out + p0 * g.sm + m * g.vin + pl * g.sm + pshift[f]
+                        out.append((dst, b, m, src))
+    return out, nb, npat, blk
+
+
+@pytest.mark.parametrize("d,p,counts", [(2, 4, (5, 3)), (2, 8, (3, 3)), (2, 16, (3, 2)),
+                                        (2, 17, (3, 2)), (2, 32, (2, 2)), (3, 4, (3, 2, 2)),
+                                        (3, 8, (3, 2, 2)), (3, 16, (2, 2, 1))])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_push_stores_fill_every_face_halo_once(d, p, counts, bc):
+    """Every face-halo slot of every output block receives exactly one push,
+    of the volume the pull-form halo fill would copy there (the facing
+    boundary volume of the neighbour, or the own boundary volume at a
+    transmissive face); no push lands on an interior, edge or corner slot."""
+    g = Geo(d, p)
+    bcs = ("periodic",) * d if bc == "periodic" else ("transmissive",) + ("periodic",) * (d - 1)
+    stores, nb, npat, blk = _push_stores(g, counts, bcs)
+    w, s = g.w, g.s
+    seen = {}
+    for dst, b, m, src in stores:
+        assert 0 <= dst < npat * blk
+        assert dst not in seen, dst
+        seen[dst] = (b, m, src)
+    want = {}
+    for b in range(npat):
+        for f in range(2 * d):
+            a, hi = f // 2, f & 1
+            n_ = nb(b, f)
+            for m in range(s):
+                for t in itertools.product(range(p), repeat=d - 1):
+                    hc = list(t[:a]) + [0] + list(t[a:])
+                    hc = [c + 1 for c in hc]
+                    hc[a] = w - 1 if hi else 0
+                    sc = [c - 1 for c in hc]
+                    if n_ >= 0:
+                        sc[a] = 0 if hi else p - 1
+                        srcp = n_
+                    else:
+                        sc[a] = p - 1 if hi else 0
+                        srcp = b
+                    idx = sum(c * w ** k for k, c in enumerate(hc))
+                    want[b * blk + m * g.vin + idx] = (srcp, m, tuple(sc))
+    assert set(seen) == set(want)
+    for k, v in want.items():
+        assert seen[k] == v, (k, seen[k], v)
