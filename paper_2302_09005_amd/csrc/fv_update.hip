@@ -67,6 +67,20 @@ __device__ __forceinline__ float uni(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// Orders the LDS accesses of a workgroup's threads at a phase boundary.  A
+// workgroup of one wave needs no barrier and no wait: the LDS performs the
+// accesses of one wave in program order, so it is enough that the compiler
+// keeps them in order (a wavefront-scope fence).
+template <int NT>
+__device__ __forceinline__ void phase_sync() {
+  if constexpr (NT == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 // Per-workgroup outputs of the update body for the caller's epilogue.
 struct BodyOut {
   double lam;    // maximum of the new state of this thread's patch (NaN if skipped)
@@ -361,7 +375,7 @@ __device__ __forceinline__ BodyOut update_body(
         cell[(S + 2) * NCELL + LANES + l] = wr.c;
       }
     }
-    __syncthreads();
+    phase_sync<G::NT>();
 
     // B. in-plane faces on the low side of each volume, plus the high boundary.
     // The boundary faces come first: their operands (two volumes from LDS)
@@ -413,7 +427,7 @@ __device__ __forceinline__ BodyOut update_body(
         rusanov<T, D, 1>(qn, wn, qc, wc, Fl1);
       }
     }
-    __syncthreads();
+    phase_sync<G::NT>();
 
     // C. publish face fluxes: face[k][m][index]
     if (act && live) {
@@ -431,7 +445,7 @@ __device__ __forceinline__ BodyOut update_body(
         for (int m = 0; m < S; ++m) face[base + m * NF] = Fx[m];
       }
     }
-    __syncthreads();
+    phase_sync<G::NT>();
 
     // D. high-side faces, marching-axis face, update, store, running maximum.
     // The x and y terms of the update are applied first, so the in-plane face
@@ -479,7 +493,7 @@ __device__ __forceinline__ BodyOut update_body(
     }
 #pragma unroll
     for (int m = 0; m < S; ++m) rraw[m] = rnext[m];
-    __syncthreads();
+    phase_sync<G::NT>();
   }
 
   // ---- per-patch maximum: shuffles within the patch's lanes ---------------
@@ -490,7 +504,7 @@ __device__ __forceinline__ BodyOut update_body(
     for (int o = seg / 2; o > 0; o >>= 1) lam = nanmax_pos(lam, T(__shfl_xor(lam, o, 64)));
     if constexpr (LANES > 64) {
       if ((tid & 63) == 0) red[tid >> 6] = lam;
-      __syncthreads();
+      phase_sync<G::NT>();
       if (tid == 0) {
 #pragma unroll
         for (int w = 1; w < LANES / 64; ++w) lam = nanmax_pos(lam, red[w]);
@@ -498,7 +512,7 @@ __device__ __forceinline__ BodyOut update_body(
     } else if constexpr (ZS > 1) {
       // fold the chunks of each patch (whole waves, or lane groups of one)
       if (l == 0 && in_patch) red[slot * ZS + chunk] = lam;
-      __syncthreads();
+      phase_sync<G::NT>();
       if (lead) {
 #pragma unroll
         for (int c = 1; c < ZS; ++c) lam = nanmax_pos(lam, red[slot * ZS + c]);
@@ -508,7 +522,7 @@ __device__ __forceinline__ BodyOut update_body(
     // odd cross-sections (e.g. 17 lanes): gather the lanes of every chunk
     // of the patch through LDS
     lds[tid < G::PPW * G::SLOT ? tid : 0] = lam;
-    __syncthreads();
+    phase_sync<G::NT>();
     if (lead) {
       for (int i = 1; i < G::TPP; ++i) lam = nanmax_pos(lam, lds[slot * G::TPP + i]);
     }
@@ -599,7 +613,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
       // below to the two results above
       dep_s[slot] = (o1 == ~0ull || o2 == ~0ull) ? 1ull : 0ull;
     }
-    __syncthreads();
+    phase_sync<G::NT>();
     if (tid == 0) {
       unsigned long long dep = 0;
 #pragma unroll
