@@ -181,8 +181,10 @@ __device__ __forceinline__ void tanh_pack(const floatx16& c, bf16x8& k0, bf16x8&
 // The network on the 64 faces of this wave: lane l holds the normalised
 // features xh[16] of face l and receives its outputs o[4].  Wave-local: the
 // LDS traffic of one wave is ordered, so no workgroup barrier is needed.
+// tiles: 2, or 1 when faces 32..63 are not needed (their outputs are left
+// as they were); the same on every lane of the wave.
 __device__ void mlp64(const MlpFrags& F, const MlpBias& B, MlpLds& s, int l,
-                      const float (&xh)[kNF], float (&o)[kNO]) {
+                      const float (&xh)[kNF], float (&o)[kNO], int tiles = 2) {
   const int j = l & 31, h = l >> 5;
   s.x[l][0] = to_bf16x8(xh);
   s.x[l][1] = to_bf16x8(xh + 8);
@@ -190,6 +192,7 @@ __device__ void mlp64(const MlpFrags& F, const MlpBias& B, MlpLds& s, int l,
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
+    if (t >= tiles) break;
     const bf16x8 xt = s.x[32 * t + j][h];  // X^T tile: features 8 h + e of face 32 t + j
     bf16x8 h1[4], h2[4];
 #pragma unroll
@@ -371,7 +374,8 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
         xh[4 * o + c] = ((float)fr[c] - blob[kXM + 4 * o + c]) * blob[kXS + 4 * o + c];
     }
     float out[kNO];
-    mlp64(F, s.bias, s.mlp[wave], l, xh, out);
+    // the last batch holds 544 - 8 * 64 = 32 faces: one tile of the network
+    mlp64(F, s.bias, s.mlp[wave], l, xh, out, (batch + 1) * 64 <= kNFACE ? 2 : 1);
     // plain flux of the face, grid axes
     double Fr[4];
     {
