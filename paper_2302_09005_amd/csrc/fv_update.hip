@@ -156,13 +156,26 @@ __device__ __forceinline__ BodyOut update_body(
   double hmin = __builtin_inf();
   double dt_used = 0.0, t_used = 0.0;
   bool ok = false;
+  // the device time step, loaded alongside the descriptor rather than after it
+  const bool dev_dt = MODE != kLocalDt && dt_dev != nullptr;
+  const double dt_d = dev_dt ? *dt_dev : 0.0;
   if (in_range) {
+    // The neighbour table row (loaded with the descriptor), then the
+    // neighbours' descriptors as one batch of independent loads (an index
+    // outside [0, n) reads the own descriptor instead and is judged below):
+    // two memory round trips before the first plane can be loaded, whatever
+    // the number of faces.
+    int64_t nbi[2 * D];
+    if constexpr (GATHER || PUSH) {
+#pragma unroll
+      for (int f = 0; f < 2 * D; ++f) nbi[f] = neighbours[b * 2 * D + f];
+    }
     const fv_patch pd = patches[b];
     off_in = pd.q_in;
     off_out = pd.q_out;
     ok = pd.p == P && off_in >= 0 && off_in <= qin_len - blk_in && off_out >= 0 &&
          off_out <= qout_len - blk_out;
-    const double dt = (MODE != kLocalDt && dt_dev) ? *dt_dev : pd.dt;
+    const double dt = dev_dt ? dt_d : pd.dt;
     dt_used = dt;
     t_used = pd.t;
 #pragma unroll
@@ -172,18 +185,24 @@ __device__ __forceinline__ BodyOut update_body(
     for (int j = 1; j < D; ++j) hmin = fmin(hmin, pd.dx[j]);
     if constexpr (GATHER) {
       // face order -x, +x, -y, +y[, -z, +z]; -1 = transmissive
+      int64_t nq[2 * D];
+      int np[2 * D];
+#pragma unroll
+      for (int f = 0; f < 2 * D; ++f) {
+        const int64_t c = (nbi[f] >= 0 && nbi[f] < n) ? nbi[f] : b;
+        nq[f] = patches[c].q_in;
+        np[f] = patches[c].p;
+      }
+      // judged without branches, so that the loads above are not sunk into
+      // a chain of conditional ones
       int64_t nbo[2 * D];
 #pragma unroll
       for (int f = 0; f < 2 * D; ++f) {
-        const int64_t nb = neighbours[b * 2 * D + f];
-        nbo[f] = -1;
-        if (nb >= 0 && nb < n) {
-          const fv_patch& pn = patches[nb];
-          if (pn.p == P && pn.q_in >= 0 && pn.q_in <= qin_len - blk_in) nbo[f] = pn.q_in;
-          else ok = false;
-        } else if (nb != -1) {
-          ok = false;
-        }
+        const int64_t nb = nbi[f];
+        const bool inr = (nb >= 0) & (nb < n);
+        const bool good = (np[f] == P) & (nq[f] >= 0) & (nq[f] <= qin_len - blk_in);
+        nbo[f] = (inr & good) ? nq[f] : -1;
+        ok = ok & (inr ? good : nb == -1);
       }
       constexpr int fl = 2 * K, fh = 2 * K + 1;  // marching-axis faces
       constexpr int last = (P - 1) * G::SMO;
@@ -211,23 +230,28 @@ __device__ __forceinline__ BodyOut update_body(
       // halo'd coordinate along the face axis: the boundary volume sits at 1
       // (low face) or P (high face); it lands at P+1 or 0 of the neighbour's
       // block, or at 0 or P+1 of the own block (transmissive)
+      // the neighbours' output offsets, sizes and back references, each as
+      // one batch of independent loads (as for the gather above)
+      int64_t nq[2 * D], back[2 * D];
+      int np[2 * D];
 #pragma unroll
       for (int f = 0; f < 2 * D; ++f) {
-        const int64_t nb = neighbours[b * 2 * D + f];
+        const int64_t c = (nbi[f] >= 0 && nbi[f] < n) ? nbi[f] : b;
+        nq[f] = patches[c].q_out;
+        np[f] = patches[c].p;
+        back[f] = neighbours[c * 2 * D + (f ^ 1)];
+      }
+#pragma unroll
+      for (int f = 0; f < 2 * D; ++f) {
+        const int64_t nb = nbi[f];
         const int64_t astride = f < 2 ? 1 : f < 4 ? W : (int64_t)W * W;
         const bool hi = f & 1;
-        if (nb >= 0 && nb < n) {
-          const fv_patch& pn = patches[nb];
-          if (pn.p == P && pn.q_out >= 0 && pn.q_out <= qout_len - blk_out &&
-              neighbours[nb * 2 * D + (f ^ 1)] == b)
-            pshift[f] = (pn.q_out - off_out) + (hi ? -P : P) * astride;
-          else
-            ok = false;
-        } else if (nb == -1) {
-          pshift[f] = hi ? astride : -astride;
-        } else {
-          ok = false;
-        }
+        const bool inr = (nb >= 0) & (nb < n);
+        const bool good = (np[f] == P) & (nq[f] >= 0) & (nq[f] <= qout_len - blk_out) &
+                          (back[f] == b);
+        pshift[f] = inr ? (nq[f] - off_out) + (hi ? -P : P) * astride
+                        : (hi ? astride : -astride);
+        ok = ok & (inr ? good : nb == -1);
       }
     }
   }
