@@ -290,17 +290,26 @@ learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   const fv_patch pd = patches[b];
   bool ok = pd.p == kP && pd.q_in >= 0 && pd.q_in <= qin_len - blk && pd.q_out >= 0 &&
             pd.q_out <= qout_len - blk;
-  int64_t nbo[4];
+  // the neighbour row, then the neighbours' descriptors, each as one batch
+  // of independent loads (an index outside [0, n) reads the own descriptor
+  // and is judged below, without branches)
+  int64_t nbi[4], nq[4], nbo[4];
+  int np[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) nbi[f] = neighbours[b * 4 + f];
+#pragma unroll
   for (int f = 0; f < 4; ++f) {
-    const int64_t nb = neighbours[b * 4 + f];
-    nbo[f] = -1;
-    if (nb >= 0 && nb < n) {
-      const fv_patch& pn = patches[nb];
-      if (pn.p == kP && pn.q_in >= 0 && pn.q_in <= qin_len - blk) nbo[f] = pn.q_in;
-      else ok = false;
-    } else if (nb != -1) {
-      ok = false;
-    }
+    const int64_t c = (nbi[f] >= 0 && nbi[f] < n) ? nbi[f] : b;
+    nq[f] = patches[c].q_in;
+    np[f] = patches[c].p;
+  }
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int64_t nb = nbi[f];
+    const bool inr = (nb >= 0) & (nb < n);
+    const bool good = (np[f] == kP) & (nq[f] >= 0) & (nq[f] <= qin_len - blk);
+    nbo[f] = (inr & good) ? nq[f] : -1;
+    ok = ok & (inr ? good : nb == -1);
   }
   if (!ok) {
     if (tid == 0 && max_eig) max_eig[b] = __builtin_nan("");

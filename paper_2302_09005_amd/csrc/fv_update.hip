@@ -323,18 +323,30 @@ __device__ __forceinline__ BodyOut update_body(
     else *dst = v;
   };
 
-  // ---- prologue: planes -1 and 0, first marching-axis face ---------------
-  T qlo[S], qc[S], qnx[S], rraw[S];
-#pragma unroll
-  for (int m = 0; m < S; ++m) {
-    qlo[m] = T(0);
-    qc[m] = T(1);
-    qnx[m] = T(1);
-    rraw[m] = T(1);
-  }
   // a patch that failed its checks skips all work (its max_eig becomes NaN)
   const bool act = ok && in_patch;
-  if (act) {
+  T lam = T(0);
+  // UNI: the workgroup marches one patch with all its threads, so act is the
+  // same in every thread and the whole march below is run or skipped; inside
+  // it nothing is conditional, and no register holds a default for a skipped
+  // load.  Otherwise every load, LDS access and update is guarded by the
+  // thread's own act.  UNI only for float state: with float64 state the
+  // scheduler's freedom in the branch-free march costs registers (3-D 8^3:
+  // 126 -> 204, two waves per SIMD instead of four); float state has room.
+  constexpr bool UNI = sizeof(T) == 4 && G::PPW == 1 && G::TPP == G::NT && !UNEVEN;
+  if (!UNI || act) {
+  // ---- prologue: planes -1 and 0, first marching-axis face ---------------
+  T qlo[S], qc[S], qnx[S], rraw[S];
+  if constexpr (!UNI) {
+#pragma unroll
+    for (int m = 0; m < S; ++m) {
+      qlo[m] = T(0);
+      qc[m] = T(1);
+      qnx[m] = T(1);
+      rraw[m] = T(1);
+    }
+  }
+  if (UNI || act) {
 #pragma unroll
     for (int m = 0; m < S; ++m) {
       qlo[m] = ld_own(0, m);
@@ -348,7 +360,6 @@ __device__ __forceinline__ BodyOut update_body(
     const Prim<T> wlo = decode<T, D>(qlo, gamma);
     rusanov<T, D, K>(qlo, wlo, qc, wc, Flo);
   }
-  T lam = T(0);
 
   // face buffers: x-faces [y][x] for the low face of every volume followed by
   // the high-boundary faces [y]; y-faces [y][x] for y in [0, P] (the last row
@@ -367,15 +378,16 @@ __device__ __forceinline__ BodyOut update_body(
   for (int pl = 0; pl < PC; ++pl) {
     // the last chunk of an uneven split idles through its missing planes
     const bool live = !UNEVEN || pl < nrows;
+    const bool run = UNI || (act && live);
     // loads for the next plane: its own volumes (needed for the
     // marching-axis face in D) and its ring (needed in the next A)
     T rnext[S];
 #pragma unroll
     for (int m = 0; m < S; ++m) {
       rnext[m] = rraw[m];
-      qnx[m] = qc[m];
+      if constexpr (!UNI) qnx[m] = qc[m];
     }
-    if (act && live) {
+    if (run) {
       if (pl + 1 < nrows) {
 #pragma unroll
         for (int m = 0; m < S; ++m) rnext[m] = ld_ring(pl + 2, m);
@@ -384,7 +396,7 @@ __device__ __forceinline__ BodyOut update_body(
       for (int m = 0; m < S; ++m) qnx[m] = ld_own(pl + 2, m);
     }
     // A. publish own and ring volumes of this plane
-    if (act && live) {
+    if (run) {
 #pragma unroll
       for (int m = 0; m < S; ++m) cell[m * NCELL + l] = qc[m];
       cell[(S + 0) * NCELL + l] = wc.ir;
@@ -406,7 +418,7 @@ __device__ __forceinline__ BodyOut update_body(
     // are then live while no other face result is, which keeps the body at
     // 4 waves per SIMD for 3-D 8^3 FP64 (126 VGPRs; 168 the other way round).
     T Fl0[S], Fl1[S], Fx[S];
-    if (act && live) {
+    if (run) {
       if (l < G::NEXTRA) {
         // high-boundary face: interior volume at coordinate P-1 against the
         // ring.  A y face reads its two in-plane momenta swapped, so that one
@@ -454,7 +466,7 @@ __device__ __forceinline__ BodyOut update_body(
     phase_sync<G::NT>();
 
     // C. publish face fluxes: face[k][m][index]
-    if (act && live) {
+    if (run) {
 #pragma unroll
       for (int m = 0; m < S; ++m) face[m * NF + fx_lo] = Fl0[m];
       if constexpr (D == 3) {
@@ -475,7 +487,7 @@ __device__ __forceinline__ BodyOut update_body(
     // The x and y terms of the update are applied first, so the in-plane face
     // fluxes are dead before the marching-axis face is evaluated (same
     // operations in the same order as one expression per unknown).
-    if (act && live) {
+    if (run) {
       T v[S];
 #pragma unroll
       for (int m = 0; m < S; ++m) {
@@ -519,6 +531,7 @@ __device__ __forceinline__ BodyOut update_body(
     for (int m = 0; m < S; ++m) rraw[m] = rnext[m];
     phase_sync<G::NT>();
   }
+  }  // the march
 
   // ---- per-patch maximum: shuffles within the patch's lanes ---------------
   constexpr bool pow2 = (LANES & (LANES - 1)) == 0;
