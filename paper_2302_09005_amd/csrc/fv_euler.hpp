@@ -50,11 +50,13 @@ __device__ __forceinline__ double recip(double x) {
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Square root from the hardware reciprocal-square-root estimate y ~ 1/sqrt(x)
-// by Goldschmidt's iteration on g ~ sqrt(x), h ~ 1/(2 sqrt(x)) followed by
-// two Newton corrections g += (x - g^2) h.  Without the range scaling of the
-// library routine: exact to the last bit or two for normal arguments, which
-// is all a sound speed needs.  Zeros and +inf map to themselves, negative
-// arguments and NaN to NaN.
+// by one step of Goldschmidt's iteration on g ~ sqrt(x), h ~ 1/(2 sqrt(x))
+// (relative error e of y becomes about 1.5 e^2) followed by one Newton
+// correction g += (x - g^2) h (error squared again, far below an ulp for any
+// estimate better than 2^-20; the last fused multiply-add rounds once, so
+// the result is within about half an ulp).  Without the range scaling of the
+// library routine, which normal arguments do not need.  Zeros and +inf map
+// to themselves, negative arguments and NaN to NaN.
 __device__ __forceinline__ double sqrt_fast(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y;
@@ -62,9 +64,7 @@ __device__ __forceinline__ double sqrt_fast(double x) {
   const double r = fma(-h, g, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
-  double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  d = fma(-g, g, x);
+  const double d = fma(-g, g, x);
   g = fma(d, h, g);
   // -0, +0 and +inf (class bits 5, 6 and 9): the iteration would give NaN
   return __builtin_amdgcn_class(x, 0x260) ? x : g;
