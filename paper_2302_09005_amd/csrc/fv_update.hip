@@ -92,7 +92,8 @@ struct BodyOut {
 
 // The update of the (up to PPW) patches of one workgroup of NTW threads, each
 // marched in ZS chunks.  b: the patch of this thread's slot (-1: none).
-// lds: PPW * ZS * SLOT elements, red: Geo::NRED elements, both shared.  MODE:
+// lds: PPW * ZS * SLOT elements, red: Geo::NRED elements, both shared by the
+// body's NTW threads, whose index in the body is tid.  MODE:
 // see StepMode (kLocalDt needs a writable descriptor array and cfl).  NTS:
 // write the new state with non-temporal stores (the same values).  PUSH
 // (halo'd input and output blocks): the halo exchange of the new state is
@@ -107,7 +108,7 @@ __device__ __forceinline__ BodyOut update_body(
     const fv_patch* __restrict__ patches, int64_t n, const int64_t* __restrict__ neighbours,
     const T* __restrict__ qin, int64_t qin_len, T* __restrict__ qout, int64_t qout_len,
     int out_halo, T gamma, const double* __restrict__ dt_dev, double* __restrict__ max_eig,
-    double cfl, int64_t b, T* __restrict__ lds, T* __restrict__ red) {
+    double cfl, int64_t b, T* __restrict__ lds, T* __restrict__ red, int tid) {
   using G = Geo<D, P, NTW, ZS>;
   constexpr int S = G::S;
   constexpr int PC = G::PC;  // planes of a chunk (the last chunk may have fewer)
@@ -121,7 +122,6 @@ __device__ __forceinline__ BodyOut update_body(
   constexpr int CS = GATHER ? G::VOUT : G::VIN;
   constexpr int PS = GATHER ? G::SMO : G::SM;
 
-  const int tid = threadIdx.x;
   const int slot = G::PPW == 1 ? 0 : tid / G::TPP;
   const int tp = G::PPW == 1 ? tid : tid - slot * G::TPP;  // thread within the patch
   const int chunk = ZS == 1 ? 0 : tp / LANES;
@@ -615,7 +615,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
       update_body<T, D, P, 64, G::CHUNKS, GATHER, MODE == kLocalDt ? kLocalDt : kPlain, NTS,
                   PUSH>(
       patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo, gamma, dt_dev, max_eig,
-      cflo.cfl, b, lds, red);
+      cflo.cfl, b, lds, red, tid);
   const double lam_b = bo.lam;
   const double hmin = bo.hmin;
   const bool lead = bo.lead;
@@ -698,46 +698,71 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
 // time step (local time stepping, kLocalDt).
 // ---------------------------------------------------------------------------
 constexpr int kMixedNT = 256;
+// A unit of 8^3 or 4^3 patches is run wave by wave: each of the four waves
+// marches its own 8^3 patch, or its own four 4^3 patches, with the one-wave
+// body (its LDS slot private, its phases ordered by wavefront fences, its
+// patch values in scalar registers); a 16^3 patch takes the whole
+// workgroup.
 template <int P>
-constexpr int mixed_lds() { return Geo<3, P, kMixedNT, 1>::PPW * Geo<3, P, kMixedNT, 1>::SLOT; }
+using MixedGeo = Geo<3, P, P == 16 ? kMixedNT : 64, 1>;
+template <int P>
+constexpr int mixed_lds() {
+  return (P == 16 ? 1 : kMixedNT / 64) * MixedGeo<P>::PPW * MixedGeo<P>::SLOT;
+}
+template <int P>
+constexpr int mixed_red() { return (P == 16 ? 1 : kMixedNT / 64) * MixedGeo<P>::NRED; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-// Two waves per SIMD: the union of the three bodies would otherwise take
-// every register and leave one.
+// The work list holds the 16^3 units first, then the 8^3 ones, then the 4^3
+// ones (u8 and u4: the first unit of each of the two later classes, from the
+// host plan).  Each size has its own loop: with the three bodies in one loop
+// the kernel needed 209 registers (two waves per SIMD); in three loops it
+// fits three waves per SIMD (167 registers, a few bytes of spills).  A unit
+// whose size or run does not match its range is skipped.
 template <typename T, bool NTS>
-__global__ void __launch_bounds__(kMixedNT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kMixedNT) __attribute__((amdgpu_waves_per_eu(3)))
 fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
                 const int64_t* __restrict__ neighbours, const T* __restrict__ qin,
                 int64_t qin_len, T* __restrict__ qout, int64_t qout_len, T gamma, double cfl,
                 double* __restrict__ max_eig, const int64_t* __restrict__ order,
-                const fv_work_unit* __restrict__ units, int64_t n_units) {
+                const fv_work_unit* __restrict__ units, int64_t n_units, int64_t u8,
+                int64_t u4) {
   __shared__ T lds[cmax(mixed_lds<16>(), cmax(mixed_lds<8>(), mixed_lds<4>()))];
-  __shared__ T red[kMixedNT / 64];
+  __shared__ T red[cmax(mixed_red<16>(), cmax(mixed_red<8>(), mixed_red<4>()))];
   const int tid = threadIdx.x;
-  for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+  const int wave = tid >> 6, lane = tid & 63;
+  auto valid = [&](const fv_work_unit& un, int p) {
+    return un.p == p && un.first >= 0 && un.count >= 0 && un.first <= n - un.count;
+  };
+  int64_t u = blockIdx.x;
+  for (; u < u8; u += gridDim.x) {
     const fv_work_unit un = units[u];
-    // a unit whose run leaves the order array is skipped (the host plan
-    // never makes one)
-    if (un.first < 0 || un.count < 0 || un.first > n - un.count) continue;
-    if (un.p == 16) {
-      const int64_t b = un.count > 0 ? order[un.first] : -1;
-      update_body<T, 3, 16, kMixedNT, 1, true, kLocalDt, NTS>(patches, n, neighbours, qin, qin_len, qout,
-                                                      qout_len, 0, gamma, nullptr, max_eig, cfl,
-                                                      b, lds, red);
-    } else if (un.p == 8) {
-      const int slot = tid / 64;
-      const int64_t b = slot < un.count ? order[un.first + slot] : -1;
-      update_body<T, 3, 8, kMixedNT, 1, true, kLocalDt, NTS>(patches, n, neighbours, qin, qin_len, qout,
-                                                     qout_len, 0, gamma, nullptr, max_eig, cfl,
-                                                     b, lds, red);
-    } else if (un.p == 4) {
-      const int slot = tid / 16;
-      const int64_t b = slot < un.count ? order[un.first + slot] : -1;
-      update_body<T, 3, 4, kMixedNT, 1, true, kLocalDt, NTS>(patches, n, neighbours, qin, qin_len, qout,
-                                                     qout_len, 0, gamma, nullptr, max_eig, cfl,
-                                                     b, lds, red);
-    }
+    if (!valid(un, 16)) continue;  // the same for the whole workgroup
+    const int64_t b = un.count > 0 ? order[un.first] : -1;
+    update_body<T, 3, 16, kMixedNT, 1, true, kLocalDt, NTS>(
+        patches, n, neighbours, qin, qin_len, qout, qout_len, 0, gamma, nullptr, max_eig, cfl,
+        b, lds, red, tid);
     __syncthreads();  // the next unit reuses the LDS
+  }
+  // the waves of the later units march separately (private LDS regions)
+  for (; u < u4; u += gridDim.x) {
+    const fv_work_unit un = units[u];
+    if (!valid(un, 8)) continue;
+    using G = MixedGeo<8>;
+    const int64_t b = wave < un.count ? order[un.first + wave] : -1;
+    update_body<T, 3, 8, 64, 1, true, kLocalDt, NTS>(
+        patches, n, neighbours, qin, qin_len, qout, qout_len, 0, gamma, nullptr, max_eig, cfl,
+        b, lds + wave * G::PPW * G::SLOT, red + wave * G::NRED, lane);
+  }
+  for (; u < n_units; u += gridDim.x) {
+    const fv_work_unit un = units[u];
+    if (!valid(un, 4)) continue;
+    using G = MixedGeo<4>;
+    const int k = wave * G::PPW + lane / G::TPP;  // patch of the unit
+    const int64_t b = k < un.count ? order[un.first + k] : -1;
+    update_body<T, 3, 4, 64, 1, true, kLocalDt, NTS>(
+        patches, n, neighbours, qin, qin_len, qout, qout_len, 0, gamma, nullptr, max_eig, cfl,
+        b, lds + wave * G::PPW * G::SLOT, red + wave * G::NRED, lane);
   }
 }
 
@@ -860,9 +885,10 @@ template int launch_step_halo<double>(const fv_patch*, int64_t, const int64_t*, 
                                       const double*, double*, const CflOut&, hipStream_t);
 
 int mixed_patches_per_unit(int p) {
-  return p == 16 ? Geo<3, 16, kMixedNT, 1>::PPW
-       : p == 8  ? Geo<3, 8, kMixedNT, 1>::PPW
-       : p == 4  ? Geo<3, 4, kMixedNT, 1>::PPW
+  // one 16^3 patch per workgroup; one 8^3 patch, or four 4^3 patches, per wave
+  return p == 16 ? MixedGeo<16>::PPW
+       : p == 8  ? (kMixedNT / 64) * MixedGeo<8>::PPW
+       : p == 4  ? (kMixedNT / 64) * MixedGeo<4>::PPW
                  : 0;
 }
 
@@ -881,16 +907,24 @@ int launch_step_local(const fv_patch* patches, int64_t n, const int64_t* neighbo
     int64_t g = grid > 0 ? grid : plan.n_units;
     if (g > plan.n_units) g = plan.n_units;
     if (g < 1) return 0;
+    // unit ranges of the size classes, as fv_plan_mixed lays them out
+    int64_t bounds[3], acc = 0;
+    for (int c = 0; c < 3; ++c) {
+      const int ppu = mixed_patches_per_unit(plan.class_p[c]);
+      acc += ppu > 0 ? (plan.class_count[c] + ppu - 1) / ppu : 0;
+      bounds[c] = acc;
+    }
+    const int64_t u8 = bounds[0], u4 = bounds[1];
     if (nts)
       hipExtLaunchKernelGGL((fv_mixed_kernel<T, true>), dim3((unsigned)g), dim3(kMixedNT), 0, st,
                             ev.start, ev.stop, 0, patches, n, neighbours, qin, qin_len, qout,
                             qout_len, T(gamma), cfl, max_eig, plan.order, plan.units,
-                            plan.n_units);
+                            plan.n_units, u8, u4);
     else
       hipExtLaunchKernelGGL((fv_mixed_kernel<T, false>), dim3((unsigned)g), dim3(kMixedNT), 0,
                             st, ev.start, ev.stop, 0, patches, n, neighbours, qin, qin_len, qout,
                             qout_len, T(gamma), cfl, max_eig, plan.order, plan.units,
-                            plan.n_units);
+                            plan.n_units, u8, u4);
     return 0;
   }
   // per size: one launch over each class's contiguous range of the sorted

@@ -79,8 +79,24 @@ def lds_elements_single(g):
     return g.ppw * g.zs * g.slot
 
 
+def mixed_geo(p):
+    """Body geometry of one work unit of the persistent mixed-size kernel: a
+    16^3 patch takes the whole 256-thread workgroup; 8^3 and 4^3 units are
+    run wave by wave with the one-wave body (one 8^3 or four 4^3 patches per
+    wave), each wave in its own LDS and reduction region."""
+    return Geo(3, p, 256, 1) if p == 16 else Geo(3, p, 64, 1)
+
+
+def mixed_waves(p):
+    return 1 if p == 16 else 4
+
+
 def lds_elements_mixed():
-    return max(Geo(3, p, 256, 1).ppw * Geo(3, p, 256, 1).slot for p in (4, 8, 16))
+    return max(mixed_waves(p) * mixed_geo(p).ppw * mixed_geo(p).slot for p in (4, 8, 16))
+
+
+def red_elements_mixed():
+    return max(mixed_waves(p) * mixed_geo(p).nred for p in (4, 8, 16))
 
 
 class Block:
@@ -258,7 +274,9 @@ def _instances():
     for (d, p), gather, out_halo in itertools.product(SINGLE, (False, True), (False, True)):
         yield Geo(d, p), lds_elements_single(Geo(d, p)), gather, out_halo, "single"
     for d, p in MIXED:
-        yield Geo(d, p, 256, 1), lds_elements_mixed(), True, False, "mixed"
+        # one wave's body (8^3, 4^3) or the workgroup's (16^3); its LDS region
+        # of the mixed kernel's array is checked against the whole array
+        yield mixed_geo(p), lds_elements_mixed(), True, False, "mixed"
 
 
 def _nb_cases(g, gather):
@@ -398,6 +416,16 @@ def test_workgroup_lds_fits_and_slots_are_disjoint():
         assert g.nred >= g.ppw * g.zs and g.nred >= g.nt // 64
         assert lds_elements_single(g) * 8 + g.nred * 8 <= 64 * 1024
     assert lds_elements_mixed() * 8 <= 64 * 1024
+    # the mixed kernel's per-wave regions: wave w of a unit owns elements
+    # [w * ppw * slot, (w + 1) * ppw * slot) and reduction entries
+    # [w * nred, (w + 1) * nred); all inside the arrays
+    for p in (4, 8):
+        g = mixed_geo(p)
+        assert g.nt == 64 and g.ppw * g.tpp == 64
+        assert mixed_waves(p) * g.ppw * g.slot <= lds_elements_mixed()
+        assert mixed_waves(p) * g.nred <= red_elements_mixed()
+    # patches per work unit, as the host plan counts them (fv_plan_mixed)
+    assert [mixed_waves(p) * mixed_geo(p).ppw for p in (16, 8, 4)] == [1, 4, 16]
 
 
 # ---------------------------------------------------------------------------
