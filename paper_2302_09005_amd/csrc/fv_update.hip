@@ -227,11 +227,11 @@ __device__ __forceinline__ BodyOut update_body(
       }
     }
     if constexpr (PUSH) {
-      // halo'd coordinate along the face axis: the boundary volume sits at 1
-      // (low face) or P (high face); it lands at P+1 or 0 of the neighbour's
-      // block, or at 0 or P+1 of the own block (transmissive)
-      // the neighbours' output offsets, sizes and back references, each as
-      // one batch of independent loads (as for the gather above)
+      // The neighbours' output offsets, sizes and back references, each as
+      // one batch of independent loads (as for the gather above).  Along the
+      // face axis a boundary volume sits at halo'd coordinate 1 (low face)
+      // or P (high face); it lands at P+1 or 0 of the neighbour's block, or
+      // at 0 or P+1 of the own block (transmissive).
       int64_t nq[2 * D], back[2 * D];
       int np[2 * D];
 #pragma unroll
@@ -754,6 +754,10 @@ fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
         patches, n, neighbours, qin, qin_len, qout, qout_len, 0, gamma, nullptr, max_eig, cfl,
         b, lds + wave * G::PPW * G::SLOT, red + wave * G::NRED, lane);
   }
+  // the 4^3 bodies lay out the LDS and reduction arrays differently: no wave
+  // may start one while another still marches an 8^3 patch (every wave of
+  // the workgroup leaves the loop above after the same units)
+  __syncthreads();
   for (; u < n_units; u += gridDim.x) {
     const fv_work_unit un = units[u];
     if (!valid(un, 4)) continue;

@@ -21,9 +21,12 @@ from the same layout rules, so a kernel edit that changes its indexing must
 be mirrored here.
 """
 import itertools
+import os
 
 import numpy as np
 import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def ceil_div(a, b):
@@ -426,6 +429,37 @@ def test_workgroup_lds_fits_and_slots_are_disjoint():
         assert mixed_waves(p) * g.nred <= red_elements_mixed()
     # patches per work unit, as the host plan counts them (fv_plan_mixed)
     assert [mixed_waves(p) * mixed_geo(p).ppw for p in (16, 8, 4)] == [1, 4, 16]
+
+
+def _regions(p, w):
+    g = mixed_geo(p)
+    lds = (w * g.ppw * g.slot, (w + 1) * g.ppw * g.slot)
+    red = (w * g.nred, (w + 1) * g.nred)
+    return lds, red
+
+
+def test_mixed_class_change_is_behind_a_workgroup_barrier():
+    """The per-wave regions of the 8^3 and 4^3 bodies overlap across waves (wave
+    w of one class writes where wave w' != w of the other reads), so the
+    persistent kernel may only change class behind a workgroup barrier: the
+    kernel source has one between every two of its class loops."""
+    overlap = lambda a, b: a[0] < b[1] and b[0] < a[1]
+    clash = False
+    for w in range(4):
+        for w2 in range(4):
+            if w == w2:
+                continue
+            l8, r8 = _regions(8, w)
+            l4, r4 = _regions(4, w2)
+            clash |= overlap(l8, l4) or overlap(r8, r4)
+    assert clash, "the regions no longer overlap; the barrier could go"
+    src = open(os.path.join(ROOT, "paper_2302_09005_amd", "csrc", "fv_update.hip")).read()
+    body = src[src.index("fv_mixed_kernel("):]
+    body = body[:body.index("\n}\n")]
+    loops = [i for i in range(len(body)) if body.startswith("for (; u <", i)]
+    assert len(loops) == 3
+    for a, b in zip(loops, loops[1:]):
+        assert "__syncthreads()" in body[a:b]
 
 
 # ---------------------------------------------------------------------------
