@@ -496,7 +496,7 @@ def uneven_path(seed, steps=50, dtype=None, tune=True, schedule=("persistent", 0
                            for p in batch.sizes))
     table = []
     if tune:
-        best, table = autotune.tune(st, steps=3, warmup=1, patchwise=True)
+        best, table = autotune.tune(st, steps=8, rounds=5, patchwise=True)
     else:
         st.schedule, st.workgroups = schedule
         best = schedule

@@ -705,13 +705,16 @@ constexpr int kMixedNT = 256;
 // workgroup.
 template <int P>
 using MixedGeo = Geo<3, P, P == 16 ? kMixedNT : 64, 1>;
-template <int P>
-constexpr int mixed_lds() {
-  return (P == 16 ? 1 : kMixedNT / 64) * MixedGeo<P>::PPW * MixedGeo<P>::SLOT;
-}
-template <int P>
-constexpr int mixed_red() { return (P == 16 ? 1 : kMixedNT / 64) * MixedGeo<P>::NRED; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// Wave w owns LDS elements [w W, (w + 1) W) and reduction entries
+// [w R, (w + 1) R) for both per-wave sizes (W, R the larger of their needs),
+// so a wave may go on from its 8^3 units to 4^3 units while the others still
+// march: no region of one wave overlaps another's.
+constexpr int kMixedWaveLds = cmax(MixedGeo<8>::PPW * MixedGeo<8>::SLOT,
+                                   MixedGeo<4>::PPW * MixedGeo<4>::SLOT);
+constexpr int kMixedWaveRed = cmax(MixedGeo<8>::NRED, MixedGeo<4>::NRED);
+constexpr int kMixedLds = cmax(MixedGeo<16>::SLOT, (kMixedNT / 64) * kMixedWaveLds);
+constexpr int kMixedRed = cmax(MixedGeo<16>::NRED, (kMixedNT / 64) * kMixedWaveRed);
 
 // The work list holds the 16^3 units first, then the 8^3 ones, then the 4^3
 // ones (u8 and u4: the first unit of each of the two later classes, from the
@@ -727,8 +730,8 @@ fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
                 double* __restrict__ max_eig, const int64_t* __restrict__ order,
                 const fv_work_unit* __restrict__ units, int64_t n_units, int64_t u8,
                 int64_t u4) {
-  __shared__ T lds[cmax(mixed_lds<16>(), cmax(mixed_lds<8>(), mixed_lds<4>()))];
-  __shared__ T red[cmax(mixed_red<16>(), cmax(mixed_red<8>(), mixed_red<4>()))];
+  __shared__ T lds[kMixedLds];
+  __shared__ T red[kMixedRed];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   auto valid = [&](const fv_work_unit& un, int p) {
@@ -744,20 +747,16 @@ fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
         b, lds, red, tid);
     __syncthreads();  // the next unit reuses the LDS
   }
-  // the waves of the later units march separately (private LDS regions)
+  // the waves of the later units march separately, each in its own LDS and
+  // reduction region (the last 16^3 unit ended with a barrier)
   for (; u < u4; u += gridDim.x) {
     const fv_work_unit un = units[u];
     if (!valid(un, 8)) continue;
-    using G = MixedGeo<8>;
     const int64_t b = wave < un.count ? order[un.first + wave] : -1;
     update_body<T, 3, 8, 64, 1, true, kLocalDt, NTS>(
         patches, n, neighbours, qin, qin_len, qout, qout_len, 0, gamma, nullptr, max_eig, cfl,
-        b, lds + wave * G::PPW * G::SLOT, red + wave * G::NRED, lane);
+        b, lds + wave * kMixedWaveLds, red + wave * kMixedWaveRed, lane);
   }
-  // the 4^3 bodies lay out the LDS and reduction arrays differently: no wave
-  // may start one while another still marches an 8^3 patch (every wave of
-  // the workgroup leaves the loop above after the same units)
-  __syncthreads();
   for (; u < n_units; u += gridDim.x) {
     const fv_work_unit un = units[u];
     if (!valid(un, 4)) continue;
@@ -766,7 +765,7 @@ fv_mixed_kernel(const fv_patch* __restrict__ patches, int64_t n,
     const int64_t b = k < un.count ? order[un.first + k] : -1;
     update_body<T, 3, 4, 64, 1, true, kLocalDt, NTS>(
         patches, n, neighbours, qin, qin_len, qout, qout_len, 0, gamma, nullptr, max_eig, cfl,
-        b, lds + wave * G::PPW * G::SLOT, red + wave * G::NRED, lane);
+        b, lds + wave * kMixedWaveLds, red + wave * kMixedWaveRed, lane);
   }
 }
 

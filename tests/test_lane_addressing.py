@@ -94,12 +94,22 @@ def mixed_waves(p):
     return 1 if p == 16 else 4
 
 
+def wave_lds_mixed():
+    """LDS elements each wave owns in the per-wave bodies: the larger of the
+    8^3 and 4^3 needs, so that wave w's region is the same for both sizes."""
+    return max(mixed_geo(p).ppw * mixed_geo(p).slot for p in (4, 8))
+
+
+def wave_red_mixed():
+    return max(mixed_geo(p).nred for p in (4, 8))
+
+
 def lds_elements_mixed():
-    return max(mixed_waves(p) * mixed_geo(p).ppw * mixed_geo(p).slot for p in (4, 8, 16))
+    return max(mixed_geo(16).slot, 4 * wave_lds_mixed())
 
 
 def red_elements_mixed():
-    return max(mixed_waves(p) * mixed_geo(p).nred for p in (4, 8, 16))
+    return max(mixed_geo(16).nred, 4 * wave_red_mixed())
 
 
 class Block:
@@ -420,46 +430,46 @@ def test_workgroup_lds_fits_and_slots_are_disjoint():
         assert lds_elements_single(g) * 8 + g.nred * 8 <= 64 * 1024
     assert lds_elements_mixed() * 8 <= 64 * 1024
     # the mixed kernel's per-wave regions: wave w of a unit owns elements
-    # [w * ppw * slot, (w + 1) * ppw * slot) and reduction entries
-    # [w * nred, (w + 1) * nred); all inside the arrays
+    # [w * W, (w + 1) * W) and reduction entries [w * R, (w + 1) * R) for
+    # both per-wave sizes; each size's needs fit its wave's region
     for p in (4, 8):
         g = mixed_geo(p)
         assert g.nt == 64 and g.ppw * g.tpp == 64
-        assert mixed_waves(p) * g.ppw * g.slot <= lds_elements_mixed()
-        assert mixed_waves(p) * g.nred <= red_elements_mixed()
+        assert g.ppw * g.slot <= wave_lds_mixed() and g.nred <= wave_red_mixed()
+    assert 4 * wave_lds_mixed() <= lds_elements_mixed()
+    assert 4 * wave_red_mixed() <= red_elements_mixed()
     # patches per work unit, as the host plan counts them (fv_plan_mixed)
     assert [mixed_waves(p) * mixed_geo(p).ppw for p in (16, 8, 4)] == [1, 4, 16]
 
 
 def _regions(p, w):
     g = mixed_geo(p)
-    lds = (w * g.ppw * g.slot, (w + 1) * g.ppw * g.slot)
-    red = (w * g.nred, (w + 1) * g.nred)
+    lds = (w * wave_lds_mixed(), w * wave_lds_mixed() + g.ppw * g.slot)
+    red = (w * wave_red_mixed(), w * wave_red_mixed() + g.nred)
     return lds, red
 
 
-def test_mixed_class_change_is_behind_a_workgroup_barrier():
-    """The per-wave regions of the 8^3 and 4^3 bodies overlap across waves (wave
-    w of one class writes where wave w' != w of the other reads), so the
-    persistent kernel may only change class behind a workgroup barrier: the
-    kernel source has one between every two of its class loops."""
+def test_mixed_waves_never_share_a_region():
+    """A wave of the persistent kernel moves from its 8^3 units to 4^3 units
+    without waiting for the other waves: the region wave w uses for either
+    size overlaps no region of another wave for either size.  (With each
+    size's own stride, 768 and 1024 doubles, they overlapped.)  The 16^3
+    units, which use the whole array, end with a workgroup barrier."""
     overlap = lambda a, b: a[0] < b[1] and b[0] < a[1]
-    clash = False
-    for w in range(4):
-        for w2 in range(4):
+    for p, p2 in itertools.product((8, 4), repeat=2):
+        for w, w2 in itertools.product(range(4), repeat=2):
             if w == w2:
                 continue
-            l8, r8 = _regions(8, w)
-            l4, r4 = _regions(4, w2)
-            clash |= overlap(l8, l4) or overlap(r8, r4)
-    assert clash, "the regions no longer overlap; the barrier could go"
+            (l1, r1), (l2, r2) = _regions(p, w), _regions(p2, w2)
+            assert not overlap(l1, l2) and not overlap(r1, r2), (p, w, p2, w2)
+    g8, g4 = mixed_geo(8), mixed_geo(4)
+    assert g8.ppw * g8.slot != g4.ppw * g4.slot  # why the common stride matters
     src = open(os.path.join(ROOT, "paper_2302_09005_amd", "csrc", "fv_update.hip")).read()
     body = src[src.index("fv_mixed_kernel("):]
     body = body[:body.index("\n}\n")]
-    loops = [i for i in range(len(body)) if body.startswith("for (; u <", i)]
-    assert len(loops) == 3
-    for a, b in zip(loops, loops[1:]):
-        assert "__syncthreads()" in body[a:b]
+    assert body.count("lds + wave * kMixedWaveLds, red + wave * kMixedWaveRed") == 2
+    first = body[body.index("for (; u < u8;"):body.index("for (; u < u4;")]
+    assert "__syncthreads()" in first
 
 
 # ---------------------------------------------------------------------------
