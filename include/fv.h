@@ -201,7 +201,7 @@ int64_t fv_step_workspace_words(int64_t n_patches, int dim, int p);
  * workspace taken from a buffer inside the library instead of an argument.
  *
  * The buffer is a static device array of FV_NOALLOC_SCRATCH_WORDS uint64
- * words (1 MiB) that every GPU the library runs on holds until the process
+ * words (3 MiB) that every GPU the library runs on holds until the process
  * ends.  The first call on a device looks up its address there and clears it
  * with a kernel on `stream`; nothing is allocated, freed or synchronised on
  * any call.  A batch whose workspace need, fv_step_workspace_words(n_patches,
@@ -213,7 +213,7 @@ int64_t fv_step_workspace_words(int64_t n_patches, int dim, int p);
  * workspace per stream.  Arguments and outputs otherwise as for
  * fv_step_gather (FP64 state).
  */
-#define FV_NOALLOC_SCRATCH_WORDS 131072
+#define FV_NOALLOC_SCRATCH_WORDS 393216
 int fv_step_gather_noalloc(const fv_patch* patches, int64_t n_patches, const int64_t* neighbours,
                            const double* q_in, int64_t q_in_len, double* q_out, int64_t q_out_len,
                            int dim, int p, int s, double gamma, double cfl,

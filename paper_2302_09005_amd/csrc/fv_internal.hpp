@@ -82,12 +82,13 @@ struct Geo {
 };
 
 // Outputs of the CFL step fused into the update (see fv_step_gather).  The
-// workspace holds (1 + groups) slot sets of kCflSlot words, each on its own
-// 256-byte line: words 0..2 = arrival count, max lambda bits, max (inf - h)
-// bits; set 0 is the top of the reduction tree, set g+1 serves group g of
-// kCflGroup consecutive workgroups.
+// workspace holds (1 + groups) slot sets of kCflSlot words: words 0,
+// kCflWord and 2 kCflWord of a set = arrival count, max lambda bits, max
+// (inf - h) bits; set 0 is the top of the reduction tree (its count only),
+// set g+1 serves group g of kCflGroup consecutive workgroups.
 constexpr int kCflGroup = 64;
-constexpr int kCflSlot = 32;
+constexpr int kCflWord = 32;  // each word on a 256-byte line of its own
+constexpr int kCflSlot = 3 * kCflWord;
 struct CflOut {
   double cfl = 0.0;
   double* dt_next = nullptr;

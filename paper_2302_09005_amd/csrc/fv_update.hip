@@ -159,6 +159,14 @@ __device__ __forceinline__ BodyOut update_body(
   // the device time step, loaded alongside the descriptor rather than after it
   const bool dev_dt = MODE != kLocalDt && dt_dev != nullptr;
   const double dt_d = dev_dt ? *dt_dev : 0.0;
+  // GATHER: the chunk's first two own planes, loaded as soon as the own
+  // descriptor has been checked, while the neighbours' descriptors are still
+  // on their way (for chunks whose march is fully unrolled; in the others the
+  // early values would stay live across the loop)
+  constexpr bool HOIST = GATHER && PC <= 8;
+  T qpre0[S], qpre1[S];
+#pragma unroll
+  for (int m = 0; m < S; ++m) qpre0[m] = qpre1[m] = T(1);
   if (in_range) {
     // The neighbour table row (loaded with the descriptor), then the
     // neighbours' descriptors as one batch of independent loads (an index
@@ -175,6 +183,17 @@ __device__ __forceinline__ BodyOut update_body(
     off_out = pd.q_out;
     ok = pd.p == P && off_in >= 0 && off_in <= qin_len - blk_in && off_out >= 0 &&
          off_out <= qout_len - blk_out;
+    if constexpr (HOIST) {
+      if (ok) {
+        const T* g0 = qin + off_in + (x + (D == 3 ? y * P : 0)) + (int64_t)p0 * PS;
+#pragma unroll
+        for (int m = 0; m < S; ++m) qpre0[m] = g0[(int64_t)m * CS];
+        if (nrows >= 2) {
+#pragma unroll
+          for (int m = 0; m < S; ++m) qpre1[m] = g0[(int64_t)m * CS + PS];
+        }
+      }
+    }
     const double dt = dev_dt ? dt_d : pd.dt;
     dt_used = dt;
     t_used = pd.t;
@@ -350,7 +369,7 @@ __device__ __forceinline__ BodyOut update_body(
 #pragma unroll
     for (int m = 0; m < S; ++m) {
       qlo[m] = ld_own(0, m);
-      qc[m] = ld_own(1, m);
+      qc[m] = HOIST ? qpre0[m] : ld_own(1, m);
       rraw[m] = ld_ring(1, m);  // lanes without a ring volume read their own column
     }
   }
@@ -393,7 +412,8 @@ __device__ __forceinline__ BodyOut update_body(
         for (int m = 0; m < S; ++m) rnext[m] = ld_ring(pl + 2, m);
       }
 #pragma unroll
-      for (int m = 0; m < S; ++m) qnx[m] = ld_own(pl + 2, m);
+      for (int m = 0; m < S; ++m)
+        qnx[m] = (HOIST && pl == 0 && nrows >= 2) ? qpre1[m] : ld_own(pl + 2, m);
     }
     // A. publish own and ring volumes of this plane
     if (run) {
@@ -624,27 +644,30 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
     // with device-scope atomic maxima of IEEE bit patterns (values >= 0 or
     // NaN, so integer order is numeric order with NaN on top, and the result
     // does not depend on the order of arrival).  Same-address atomics
-    // serialize, so the fold is a two-level tree: the workgroups of a group
-    // (kCflGroup consecutive ones) fold into the group's slots, the last to
-    // arrive folds the group's totals into the top slots, and the last group
-    // to arrive computes the next time step.  Every slot is cleared by the
-    // workgroup that consumed it.  Ordering without fences: the maxima are
-    // returning atomics whose results feed the arrival increment, so a fold
-    // is counted only after it has been performed.
+    // serialize, so the workgroups fold into the slots of their group
+    // (kCflGroup consecutive ones) and count their arrival there; the last of
+    // a group counts the group's arrival at the top, and the last group to
+    // arrive reads (and clears) every group's slots, one group per lane, and
+    // computes the next time step: four dependent atomic round trips from
+    // the last workgroup's fold to the time step.  Ordering without fences:
+    // the maxima are returning atomics whose results feed the arrival
+    // increment, so a fold is counted only after it has been performed, and
+    // each later step is issued only after the count before it returned.
     __shared__ unsigned long long dep_s[G::PPW];
-    __shared__ int stage;  // 1: last of its group, 2: last group overall
+    __shared__ int last;  // this workgroup is the last of the launch to arrive
     const unsigned nwg = gridDim.x;
     const unsigned grp = blockIdx.x / kCflGroup;
     const unsigned ngrp = (nwg + kCflGroup - 1) / kCflGroup;
     const unsigned gsize = min((unsigned)kCflGroup, nwg - grp * kCflGroup);
     unsigned long long* gs = cflo.ws + (size_t)kCflSlot * (grp + 1);  // group slots
     unsigned long long* ts = cflo.ws;                                 // top slots
+    constexpr int kC = 0, kL = kCflWord, kH = 2 * kCflWord;  // count, max lambda, max (inf - h)
     if (lead) {
       const unsigned long long o1 = __hip_atomic_fetch_max(
-          &gs[1], (unsigned long long)__double_as_longlong(lam_b), __ATOMIC_RELAXED,
+          &gs[kL], (unsigned long long)__double_as_longlong(lam_b), __ATOMIC_RELAXED,
           __HIP_MEMORY_SCOPE_AGENT);
       const unsigned long long o2 = __hip_atomic_fetch_max(
-          &gs[2], kInfBits - (unsigned long long)__double_as_longlong(hmin),
+          &gs[kH], kInfBits - (unsigned long long)__double_as_longlong(hmin),
           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // never true (no maximum reaches all ones); it only ties the arrival
       // below to the two results above
@@ -657,33 +680,39 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
       for (int k = 0; k < G::PPW; ++k)
         if (wgi * G::PPW + k < count) dep |= dep_s[k];
       const unsigned long long before =
-          __hip_atomic_fetch_add(&gs[0], 1ull + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      stage = before == gsize - 1 ? 1 : 0;
-      if (stage) {
-        // last of the group: move the group's totals to the top
-        const unsigned long long lb =
-            __hip_atomic_exchange(&gs[1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long hb =
-            __hip_atomic_exchange(&gs[2], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_exchange(&gs[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long t1 =
-            __hip_atomic_fetch_max(&ts[1], lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long t2 =
-            __hip_atomic_fetch_max(&ts[2], hb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long tdep = (t1 == ~0ull || t2 == ~0ull) ? 1ull : 0ull;
+          __hip_atomic_fetch_add(&gs[kC], 1ull + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int l = 0;
+      if (before == gsize - 1) {
+        // last of its group: every fold of the group has been performed
+        __hip_atomic_store(&gs[kC], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long tb =
-            __hip_atomic_fetch_add(&ts[0], 1ull + tdep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (tb == ngrp - 1) {
-          const unsigned long long Lb =
-              __hip_atomic_exchange(&ts[1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const unsigned long long Hb =
-              __hip_atomic_exchange(&ts[2], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_exchange(&ts[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const double L = __longlong_as_double((long long)Lb);
-          const double h = __longlong_as_double((long long)(kInfBits - Hb));
-          *cflo.dt_next = cflo.cfl * h / ((double)D * L);
-          if (cflo.lambda_out) *cflo.lambda_out = L;
-        }
+            __hip_atomic_fetch_add(&ts[kC], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        l = tb == ngrp - 1;
+        if (l) __hip_atomic_store(&ts[kC], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      last = l;
+    }
+    phase_sync<G::NT>();
+    if (last && tid < 64) {
+      // every group has counted its arrival: read and clear all their slots
+      unsigned long long Lb = 0, Hb = 0;
+      for (unsigned g = tid; g < ngrp; g += 64) {
+        unsigned long long* s = cflo.ws + (size_t)kCflSlot * (g + 1);
+        Lb = max(Lb, __hip_atomic_exchange(&s[kL], 0ull, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT));
+        Hb = max(Hb, __hip_atomic_exchange(&s[kH], 0ull, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT));
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        Lb = max(Lb, (unsigned long long)__shfl_xor(Lb, o, 64));
+        Hb = max(Hb, (unsigned long long)__shfl_xor(Hb, o, 64));
+      }
+      if (tid == 0) {
+        const double L = __longlong_as_double((long long)Lb);
+        const double h = __longlong_as_double((long long)(kInfBits - Hb));
+        *cflo.dt_next = cflo.cfl * h / ((double)D * L);
+        if (cflo.lambda_out) *cflo.lambda_out = L;
       }
     }
   }

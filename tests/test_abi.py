@@ -136,11 +136,12 @@ def test_other_entry_points_reject_bad_arguments_on_host():
 
 def test_step_workspace_size_and_rejection_on_host():
     lib = fv.library()
-    assert fv.step_workspace_words(4096, 3, 8) == 32 * (1 + 64)
-    assert fv.step_workspace_words(64, 2, 16) == 32 * 2   # one patch (4 row chunks) per workgroup
-    assert fv.step_workspace_words(100, 2, 16) == 32 * 3  # 100 workgroups: two groups + top
-    assert fv.step_workspace_words(100, 2, 17) == 32 * 3  # one patch (3 row chunks) each
-    assert fv.step_workspace_words(100, 2, 8) == 32 * 2   # 8 patches per workgroup: 13
+    # 96 words (three 256-byte lines) per group of 64 workgroups, plus the top
+    assert fv.step_workspace_words(4096, 3, 8) == 96 * (1 + 64)
+    assert fv.step_workspace_words(64, 2, 16) == 96 * 2   # one patch (4 row chunks) per workgroup
+    assert fv.step_workspace_words(100, 2, 16) == 96 * 3  # 100 workgroups: two groups + top
+    assert fv.step_workspace_words(100, 2, 17) == 96 * 3  # one patch (3 row chunks) each
+    assert fv.step_workspace_words(100, 2, 8) == 96 * 2   # 8 patches per workgroup: 13
     assert fv.step_workspace_words(0, 3, 8) == 0 and fv.step_workspace_words(10, 3, 5) == 0
     args = [0x1000, 4096, 0x2000, 0x10000, 1000, 0x100000, 1000, 3, 8, 5, 1.4, 0.4, 0x3000, None,
             0x4000]
@@ -155,10 +156,11 @@ def test_step_workspace_size_and_rejection_on_host():
 
 def test_step_noalloc_refuses_batches_beyond_its_scratch_on_host():
     lib = fv.library()
-    # 3-D 8^3: one patch per workgroup, 32 words per 64 workgroups plus 32
-    limit = (131072 // 32 - 1) * 64
-    assert fv.step_workspace_words(limit, 3, 8) == 131072
-    assert fv.step_workspace_words(limit + 1, 3, 8) > 131072
+    # 3-D 8^3: one patch per workgroup, 96 words per 64 workgroups plus 96
+    limit = (393216 // 96 - 1) * 64
+    assert limit == 262080
+    assert fv.step_workspace_words(limit, 3, 8) == 393216
+    assert fv.step_workspace_words(limit + 1, 3, 8) > 393216
     args = [0x1000, limit + 1, 0x2000, 0x10000, 1000, 0x100000, 1000, 3, 8, 5, 1.4, 0.4, 0x3000,
             None, 0x4000, None, None]
     assert lib.fv_step_gather_noalloc(*args) == fv.FV_EINVAL
