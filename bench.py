@@ -247,11 +247,37 @@ def halo_step_path(grid, q, steps, warmup, ramp_s):
             "hbm_frac": (bpc + halo_bpc) * grid.cells / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
 
 
+def fused_step_path(grid, q, steps, warmup, ramp_s):
+    """The headline workload with fv_step_gather (the CFL reduction finished
+    at the end of each launch by the last workgroup to arrive) instead of the
+    pipelined step: the same results bit for bit, timed the same way."""
+    import torch
+    from paper_2302_09005_amd import fv
+    st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
+                    grid.pack_compact(q), dim=grid.d, p=grid.p, mode="fused")
+    for _ in range(warmup):
+        st.step()
+    stream = torch.cuda.current_stream()
+    graph = StepGraphs(st, steps)
+    ramp(graph, ramp_s)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    graph.replay()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1)
+    graph.finish()
+    del graph, st
+    us = total * 1e3 / steps
+    return {"steps": steps, "step_us": us, "cell_updates_per_s": grid.cells / (us * 1e-6)}
+
+
 def profile_kernels(seed, reps):
     """Every hot kernel `reps` times on its benchmarked workload, eager, for
     counter collection under rocprofv3 (the counters are per dispatch): the
-    fused FP64 step on 32 768 x 8^3 (out of cache); the fused FP64 and FP32
-    steps and the FP64 one-launch halo'd step on 4096 x 8^3; the paper's
+    pipelined FP64 step on 32 768 x 8^3 (out of cache); the pipelined and the
+    fused FP64 and FP32 steps and the FP64 one-launch halo'd step on 4096 x
+    8^3; the paper's
     interface (CFL reduction, halo'd update, halo fill); the learned update on
     4096 patches of 16^2 with an untrained network (the same instructions as
     a trained one)."""
@@ -262,13 +288,14 @@ def profile_kernels(seed, reps):
     grid, q = W.grid_3d_random_smooth(16, 8, seed=seed)
     big = W.PatchGrid(3, 8, (32, 32, 32), 1.0 / 256)
     st = fv.Stepper(big.descriptors(out_halo=False, in_halo=False), big.neighbours(),
-                    big.pack_compact(np.tile(q, (1, 2, 2, 2))), dim=3, p=8, mode="fused")
+                    big.pack_compact(np.tile(q, (1, 2, 2, 2))), dim=3, p=8, mode="pipelined")
     for _ in range(reps):
         st.step()
     torch.cuda.synchronize()
-    print(f"profiled fused float64 on {big.n} patches: {reps} steps", flush=True)
+    print(f"profiled pipelined float64 on {big.n} patches: {reps} steps", flush=True)
     del st
-    for mode, dtype in (("fused", np.float64), ("fused", np.float32), ("halo", np.float64),
+    for mode, dtype in (("pipelined", np.float64), ("pipelined", np.float32),
+                        ("fused", np.float64), ("fused", np.float32), ("halo", np.float64),
                         ("halo_step", np.float64)):
         halo = mode.startswith("halo")
         st = fv.Stepper(grid.descriptors(out_halo=halo, in_halo=halo), grid.neighbours(),
@@ -299,21 +326,29 @@ def profile_kernels(seed, reps):
 
 class StepGraphs:
     """``steps`` steps of a ping-pong stepper (update + swap) captured as HIP
-    graphs.  A step swaps the two state (and time-step) buffers, so an odd
-    step count ends in the other buffer than it started: then two graphs are
-    captured, one starting from each buffer, and replays alternate between
-    them, so that every replay continues the run exactly ``steps`` steps
-    further.  ``finish()`` re-aligns the stepper's buffer roles with the data
-    after the replays."""
+    graphs.  The launch arguments of a stepper repeat every
+    ``st.graph_period()`` steps (2: the state and time-step buffers swap each
+    step; 6 for the pipelined step, whose CFL slot set also cycles through
+    three), so when ``steps`` is not a multiple of the period, one graph per
+    start position in the cycle is captured and replays take them in turn,
+    so that every replay continues the run exactly ``steps`` steps further.
+    ``finish()`` sets the stepper's host side to where the data is after the
+    replays."""
 
     def __init__(self, st, steps):
+        import math
         import torch
         self.st, self.steps, self.replays = st, steps, 0
+        if st.mode == "pipelined" and st.position() == 0:
+            raise ValueError("take the first pipelined step (it reads the given dt) before "
+                             "capturing")
+        self.k0 = st.position()
+        period = st.graph_period()
         self.graphs = []
         stream = torch.cuda.current_stream()
         side = torch.cuda.Stream()
         side.wait_stream(stream)
-        for _ in range(1 if steps % 2 == 0 else 2):
+        for _ in range(period // math.gcd(steps, period)):
             g = torch.cuda.CUDAGraph()
             with torch.cuda.stream(side):
                 with torch.cuda.graph(g, stream=side):
@@ -322,8 +357,9 @@ class StepGraphs:
                         st.swap()
             self.graphs.append(g)
         stream.wait_stream(side)
-        # capturing an even number of steps in total leaves the stepper's
-        # buffer roles where they were
+        # the graphs together cover a multiple of the period: the launch
+        # arguments of the next step are those of the first captured one
+        st.seek(self.k0)
 
     def replay(self):
         self.graphs[self.replays % len(self.graphs)].replay()
@@ -331,8 +367,7 @@ class StepGraphs:
 
     def finish(self):
         """After the last replay: the data moved replays * steps steps."""
-        if (self.replays * self.steps) % 2:
-            self.st.swap()
+        self.st.seek(self.k0 + self.replays * self.steps)
         self.graphs = []
 
 
@@ -377,7 +412,7 @@ def fp32_vs_fp64(grid, q, checkpoints=(1, 10, 100)):
 
 
 def fp32_path(grid, q, steps, warmup, ramp_s):
-    """The same fused step with FP32 state (FP64 maxima / CFL), timed exactly
+    """The same pipelined step with FP32 state (FP64 maxima / CFL), timed exactly
     as the FP64 line (eager warm-up, a graph of the timed steps, untimed
     replays for ramp_s seconds, one timed replay): throughput, kernel time,
     roofline at the FP32 algorithmic bytes; and the relative differences to
@@ -385,8 +420,9 @@ def fp32_path(grid, q, steps, warmup, ramp_s):
     import torch
     from paper_2302_09005_amd import fv
     st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
-                    grid.pack_compact(q), dim=grid.d, p=grid.p, mode="fused", dtype=np.float32)
-    for _ in range(warmup):
+                    grid.pack_compact(q), dim=grid.d, p=grid.p, mode="pipelined",
+                    dtype=np.float32)
+    for _ in range(max(1, warmup)):
         st.step()
     stream = torch.cuda.current_stream()
     graph = StepGraphs(st, steps)
@@ -413,7 +449,7 @@ def fp32_path(grid, q, steps, warmup, ramp_s):
 
 
 def out_of_cache_path(q, steps=20, ramp_s=0.3):
-    """The headline's fused FP64 step on 32 768 patches of 8^3: the 4096-patch
+    """The headline's pipelined FP64 step on 32 768 patches of 8^3: the 4096-patch
     field tiled 2 x 2 x 2 over a periodic 256^3 grid (dx = 1/256).  The two
     state buffers (2 x 671 MB) cannot stay in the 256 MB Infinity Cache, so
     every step streams its state from HBM (the launch writes with streaming
@@ -424,7 +460,7 @@ def out_of_cache_path(q, steps=20, ramp_s=0.3):
     from paper_2302_09005_amd import workloads as W
     grid = W.PatchGrid(3, 8, (32, 32, 32), 1.0 / 256)
     st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
-                    grid.pack_compact(np.tile(q, (1, 2, 2, 2))), dim=3, p=8, mode="fused")
+                    grid.pack_compact(np.tile(q, (1, 2, 2, 2))), dim=3, p=8, mode="pipelined")
     for _ in range(3):
         st.step()
     stream = torch.cuda.current_stream()
@@ -836,14 +872,16 @@ def main():
     grid, q = W.grid_3d_random_smooth(16, 8, seed=args.seed)
     d, p, s = grid.d, grid.p, grid.s
     desc = grid.descriptors(out_halo=False, in_halo=False)
-    st = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=d, p=p, mode="fused")
+    st = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=d, p=p, mode="pipelined")
     torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
+    # (the first pipelined step takes the constructor's time step and is not
+    # capturable: at least one eager step)
+    for _ in range(max(1, args.warmup)):
         st.step()
     torch.cuda.synchronize()
 
-    # The timed region: the K steps captured once as a HIP graph (one fused
+    # The timed region: the K steps captured as HIP graphs (one pipelined
     # kernel node per step, so the steps run back to back without host
     # launch gaps), replayed untimed for ramp_s seconds (sustained clock)
     # and once timed with events on the stream that runs it.  The per-launch kernel time is the timed replay
@@ -882,6 +920,10 @@ def main():
     finite = bool(torch.isfinite(state).all().item())
     lam_final = st.lam.item()
 
+    # the same steps with the CFL reduction at the end of each launch
+    # (fv_step_gather), timed the same way
+    fused = fused_step_path(grid, q, args.steps, args.warmup, args.ramp_s)
+    fused["pipelined_speedup"] = fused["step_us"] / (total_ms * 1e3 / args.steps)
     # the paper's interface for comparison: halo'd blocks, update + separate halo fill
     plain = plain_path(grid, q, min(args.steps, 20))
     plain["one_launch_step"] = halo_step_path(grid, q, args.steps, args.warmup, args.ramp_s)
@@ -931,10 +973,12 @@ def main():
         "data": "synthetic (seeded random smooth 3-D Euler fields)",
         "config": {"workload": "3d-euler-fp64-4096x8^3-periodic", "patches": grid.n, "p": p,
                    "d": d, "s": s, "halo": 1, "dx": grid.dx, "cfl": st.cfl, "seed": args.seed,
-                   "step": "fv_step_gather: update + halo exchange + next CFL step, one launch"},
+                   "step": "fv_step_gather_pipelined: update + halo exchange + CFL step "
+                           "(maxima folded in one launch, reduced in the next), one launch "
+                           "per step"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fv_update_kernel<double,3,8,GATHER,CFL,NTS=false>",
+                     "kernel": "fv_update_kernel<double,3,8,GATHER,PIPELINED_CFL,NTS=false>",
                      "bound_measured": "at 4096 patches the state (2 x 84 MB) stays in the 256 MB "
                                        "Infinity Cache and the kernel is bound inside the CU "
                                        "(VALU busy 45 %, LDS bank conflicts 23 % of LDS cycles, "
@@ -951,6 +995,7 @@ def main():
                    "eager_dispatch_event_us": eager_dispatch_us,
                    "eager_step_us": eager_step_us,
                    "final_lambda": lam_final, "state_finite": finite,
+                   "fused_step": fused,
                    "out_of_cache_32768": out_of_cache,
                    "plain_halo_path": plain,
                    "fp32_path": f32,

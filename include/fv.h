@@ -195,6 +195,51 @@ int fv_step_gather(const fv_patch* patches, int64_t n_patches, const int64_t* ne
 int64_t fv_step_workspace_words(int64_t n_patches, int dim, int p);
 
 /*
+ * fv_step_gather_pipelined -- the step of fv_step_gather in ONE launch, with
+ * the CFL reduction moved across the launch boundary: a call takes the time
+ * step from the per-patch maxima the PREVIOUS call folded (Lambda = max_b of
+ * the previous new state's maxima, dt = cfl * min dx / (dim * Lambda), the
+ * same value fv_step_gather writes to dt_next, bit for bit), and folds the
+ * maxima of its own new state for the next call with atomic maxima that
+ * nothing waits for.  The fused step's arrival counting at the end of the
+ * launch (four dependent device-scope round trips after the last patch) is
+ * gone; the previous maxima are loaded with the descriptors and reduced in
+ * the wave before the first update.  Same update (Section 2, eqs. (3)-(5),
+ * Algorithm 1), same CFL rule (Section 4: the step size comes from the
+ * maximal eigenvalue), same results as a run of fv_step_gather.
+ *
+ * phase       0, 1 or 2: the calls of one run pass 0, 1, 2, 0, 1, ... (the
+ *             workspace holds three slot sets: a call reads set (phase+2)%3,
+ *             folds into set `phase` and clears set (phase+1)%3)
+ * dt_in       device [1] or NULL: the time step to take; given on the FIRST
+ *             call of a run (there are no previous maxima), NULL afterwards
+ * dt_used     device [1] or NULL: receives the time step this call took
+ * lambda_out  device [1] or NULL: receives the Lambda that time step came
+ *             from (not written when dt_in is given)
+ * max_eig     device [n_patches] or NULL: per-patch maxima of the new state
+ * workspace   device uint64 [workspace_words], at least
+ *             fv_step_pipelined_workspace_words(n_patches, dim, p) words
+ *             (FV_EINVAL otherwise), all zero before the first call of a run
+ *             (a run that continues the phase sequence of an earlier one may
+ *             reuse it as that run left it); every call of a run passes the
+ *             same batch (patches, n_patches).  Calls that overlap in time
+ *             must use different workspaces.
+ * The other arguments are as for fv_step_gather; NaN maxima give a NaN time
+ * step, as there.  The time step for a call after the last one, if wanted, is
+ * fv_cfl_timestep over max_eig.
+ */
+int fv_step_gather_pipelined(const fv_patch* patches, int64_t n_patches,
+                             const int64_t* neighbours, const double* q_in, int64_t q_in_len,
+                             double* q_out, int64_t q_out_len, int dim, int p, int s,
+                             double gamma, double cfl, int phase, const double* dt_in,
+                             double* dt_used, double* max_eig, double* lambda_out,
+                             uint64_t* workspace, int64_t workspace_words, void* stream);
+
+/* Size in uint64 words of the workspace fv_step_gather_pipelined needs (0 on
+ * bad arguments): three sets of 16 slots, 4608 words for any batch size. */
+int64_t fv_step_pipelined_workspace_words(int64_t n_patches, int dim, int p);
+
+/*
  * fv_step_gather_noalloc -- fv_step_gather for callers that cannot allocate
  * device memory (code under HIP graph capture, serving loops, harnesses that
  * forbid hipMalloc): the same kernel and results, bit for bit, with the
@@ -276,6 +321,12 @@ int fv_step_gather_f32(const fv_patch* patches, int64_t n_patches, const int64_t
                        const double* dt_dev, double* max_eig, double* dt_next,
                        double* lambda_out, uint64_t* workspace, int64_t workspace_words,
                        void* stream);
+int fv_step_gather_pipelined_f32(const fv_patch* patches, int64_t n_patches,
+                                 const int64_t* neighbours, const float* q_in, int64_t q_in_len,
+                                 float* q_out, int64_t q_out_len, int dim, int p, int s,
+                                 double gamma, double cfl, int phase, const double* dt_in,
+                                 double* dt_used, double* max_eig, double* lambda_out,
+                                 uint64_t* workspace, int64_t workspace_words, void* stream);
 int fv_max_eigenvalue_f32(const fv_patch* patches, int64_t n_patches,
                           const float* q, int64_t q_len, int q_halo, int which_offsets,
                           int dim, int p, int s, double gamma,

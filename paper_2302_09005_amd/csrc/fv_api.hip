@@ -201,6 +201,39 @@ int step_gather_impl(const char* name, const fv_patch* patches, int64_t n,
 }
 
 template <typename T>
+int step_pipelined_impl(const char* name, const fv_patch* patches, int64_t n,
+                        const int64_t* neighbours, const T* q_in, int64_t q_in_len, T* q_out,
+                        int64_t q_out_len, int dim, int p, int s, double gamma, double cfl,
+                        int phase, const double* dt_in, double* dt_used, double* max_eig,
+                        double* lambda_out, uint64_t* workspace, int64_t workspace_words,
+                        void* stream) {
+  int rc = check_shape(dim, p, 1, s);
+  if (rc) return rc;
+  if (n < 1) return fail(FV_EINVAL, "n_patches must be >= 1");
+  if (!(gamma > 1.0) || !isfinite(gamma)) return fail(FV_EINVAL, "gamma must be > 1");
+  if (!(cfl > 0.0) || !isfinite(cfl)) return fail(FV_EINVAL, "cfl must be finite and > 0");
+  if (phase < 0 || phase > 2) return fail(FV_EINVAL, "phase must be 0, 1 or 2");
+  if (!patches || !neighbours || !q_in || !q_out || !workspace)
+    return fail(FV_EINVAL, "null device pointer");
+  const int64_t need = fvk::pipelined_workspace_words();
+  if (workspace_words < need) return fail(FV_EINVAL, "workspace needs %lld words", (long long)need);
+  if (q_in_len < 0 || q_out_len < 0) return fail(FV_EINVAL, "negative buffer length");
+  if (n > (int64_t)0x7fffffff) return fail(FV_EINVAL, "too many patches for one launch");
+  if ((rc = overlap_check(q_in, q_in_len, q_out, q_out_len))) return rc;
+  fvk::CflOut co;
+  co.cfl = cfl;
+  co.lambda_out = lambda_out;
+  co.ws = reinterpret_cast<unsigned long long*>(workspace);
+  co.phase = phase;
+  co.dt_in = dt_in;
+  co.dt_used = dt_used;
+  rc = fvk::launch_step_pipelined<T>(patches, n, neighbours, q_in, q_in_len, q_out, q_out_len,
+                                     dim, p, gamma, max_eig, co, (hipStream_t)stream);
+  if (rc) return fail(rc, "no kernel instance for dim=%d p=%d", dim, p);
+  return launched(name);
+}
+
+template <typename T>
 int max_eigenvalue_impl(const char* name, const fv_patch* patches, int64_t n, const T* q,
                         int64_t q_len, int q_halo, int which, int dim, int p, int s, double gamma,
                         double* per_patch, double* global, void* stream) {
@@ -425,6 +458,33 @@ int fv_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighbours
   return step_gather_impl("fv_step_gather", patches, n, neighbours, q_in, q_in_len, q_out,
                           q_out_len, dim, p, s, gamma, cfl, dt_dev, max_eig, dt_next, lambda_out,
                           workspace, workspace_words, stream);
+}
+
+int64_t fv_step_pipelined_workspace_words(int64_t n, int dim, int p) {
+  if (n < 1 || !fvk::update_supported(dim, p)) return 0;
+  return fvk::pipelined_workspace_words();
+}
+
+int fv_step_gather_pipelined(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                             const double* q_in, int64_t q_in_len, double* q_out,
+                             int64_t q_out_len, int dim, int p, int s, double gamma, double cfl,
+                             int phase, const double* dt_in, double* dt_used, double* max_eig,
+                             double* lambda_out, uint64_t* workspace, int64_t workspace_words,
+                             void* stream) {
+  return step_pipelined_impl("fv_step_gather_pipelined", patches, n, neighbours, q_in, q_in_len,
+                             q_out, q_out_len, dim, p, s, gamma, cfl, phase, dt_in, dt_used,
+                             max_eig, lambda_out, workspace, workspace_words, stream);
+}
+
+int fv_step_gather_pipelined_f32(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                                 const float* q_in, int64_t q_in_len, float* q_out,
+                                 int64_t q_out_len, int dim, int p, int s, double gamma,
+                                 double cfl, int phase, const double* dt_in, double* dt_used,
+                                 double* max_eig, double* lambda_out, uint64_t* workspace,
+                                 int64_t workspace_words, void* stream) {
+  return step_pipelined_impl("fv_step_gather_pipelined_f32", patches, n, neighbours, q_in,
+                             q_in_len, q_out, q_out_len, dim, p, s, gamma, cfl, phase, dt_in,
+                             dt_used, max_eig, lambda_out, workspace, workspace_words, stream);
 }
 
 }  // extern "C"

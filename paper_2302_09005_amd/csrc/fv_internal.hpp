@@ -94,6 +94,12 @@ struct CflOut {
   double* dt_next = nullptr;
   double* lambda_out = nullptr;
   unsigned long long* ws = nullptr;
+  // pipelined step (kPipelinedCfl): slot sets 0..2 of kPipeSlots slots each;
+  // this launch reads set (phase + 2) % 3 (unless dt_in is given), folds into
+  // set phase and clears set (phase + 1) % 3; dt_used receives the step it took
+  int phase = 0;
+  const double* dt_in = nullptr;
+  double* dt_used = nullptr;
 };
 
 // Workgroups of the update launch and the workspace words fv_step_gather needs.
@@ -101,6 +107,13 @@ int64_t update_workgroups(int dim, int p, int64_t n);
 inline int64_t step_workspace_words(int64_t workgroups) {
   return (int64_t)kCflSlot * (1 + (workgroups + kCflGroup - 1) / kCflGroup);
 }
+// The pipelined step's three slot sets: workgroup w folds into slot
+// w mod kPipeSlots of a set (no arrival counting, so a slot only needs to
+// keep up with the rate at which workgroups finish), and every wave of the
+// next launch reads the kPipeSlots slots of that set: a fixed cost per wave
+// whatever the batch size.
+constexpr int kPipeSlots = 16;
+inline int64_t pipelined_workspace_words() { return (int64_t)3 * kPipeSlots * kCflSlot; }
 
 // Events recorded by the dispatch of the next update launches (set through
 // fv_set_launch_events; null = not recorded).  Per calling thread.
@@ -117,6 +130,9 @@ enum StepMode : int {
   kLocalDt = 2,    // per-patch dt from the descriptor; the launch advances the
                    // descriptor's t by it and stores the patch's next local
                    // CFL step in its dt (local time stepping)
+  kPipelinedCfl = 3,  // dt from the maxima the previous launch folded (or a
+                      // given dt); this launch's maxima folded for the next
+                      // one, with no wait for the fold at the end
 };
 
 // Status for launchers: 0 ok, FV_EUNSUPPORTED when (dim, p) has no instance.
@@ -135,6 +151,11 @@ int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighb
                        const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int dim, int p,
                        double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
                        hipStream_t st);
+template <typename T>
+int launch_step_pipelined(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                          const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int dim,
+                          int p, double gamma, double* max_eig, const CflOut& cflo,
+                          hipStream_t st);
 
 // One whole step of the paper's layout (halo'd input and output blocks): the
 // update, its face-halo exchange pushed into the output halos, and the next

@@ -46,6 +46,7 @@
 #include "fv_euler.hpp"
 #include "fv_internal.hpp"
 
+
 namespace fvk {
 
 namespace {
@@ -88,6 +89,8 @@ struct BodyOut {
   bool in_range; // this thread's slot holds a patch
   bool lead;     // this thread carries its patch's results (lam valid here)
   int slot;      // slot of this thread in the workgroup
+  double dt;     // pipelined step: the time step taken (every thread)
+  double lprev;  // pipelined step: Lambda it was computed from (NaN with a given dt)
 };
 
 // The update of the (up to PPW) patches of one workgroup of NTW threads, each
@@ -108,7 +111,8 @@ __device__ __forceinline__ BodyOut update_body(
     const fv_patch* __restrict__ patches, int64_t n, const int64_t* __restrict__ neighbours,
     const T* __restrict__ qin, int64_t qin_len, T* __restrict__ qout, int64_t qout_len,
     int out_halo, T gamma, const double* __restrict__ dt_dev, double* __restrict__ max_eig,
-    double cfl, int64_t b, T* __restrict__ lds, T* __restrict__ red, int tid) {
+    double cfl, int64_t b, T* __restrict__ lds, T* __restrict__ red, int tid,
+    const unsigned long long* __restrict__ prev_slots = nullptr) {
   using G = Geo<D, P, NTW, ZS>;
   constexpr int S = G::S;
   constexpr int PC = G::PC;  // planes of a chunk (the last chunk may have fewer)
@@ -159,6 +163,40 @@ __device__ __forceinline__ BodyOut update_body(
   // the device time step, loaded alongside the descriptor rather than after it
   const bool dev_dt = MODE != kLocalDt && dt_dev != nullptr;
   const double dt_d = dev_dt ? *dt_dev : 0.0;
+  // Pipelined step: the slot maxima the previous launch folded, one slot per
+  // lane, loaded before the descriptor (so they have arrived when the
+  // descriptor has).  The previous launch has completed, so its atomics are
+  // visible to ordinary loads, which the workgroups of an XCD then serve from
+  // that XCD's L2 (device-scope loads of every workgroup would all go to the
+  // same few lines in memory).
+  constexpr bool PIPE = MODE == kPipelinedCfl;
+  unsigned long long pL = 0, pH = 0;
+  if constexpr (PIPE) {
+    const int sl = tid & 63;
+    if (prev_slots && sl < kPipeSlots) {
+      pL = prev_slots[(size_t)kCflSlot * sl + kCflWord];
+      pH = prev_slots[(size_t)kCflSlot * sl + 2 * kCflWord];
+    }
+  }
+  double lprev = __builtin_nan("");
+  // dt = cfl * min dx / (D * Lambda) over the previous launch's maxima,
+  // exactly as the fused step computes it at its end (every lane of the wave
+  // takes part)
+  auto pipe_dt = [&]() -> double {
+    if (!prev_slots) return dt_d;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      pL = max(pL, (unsigned long long)__shfl_xor(pL, o, 64));
+      pH = max(pH, (unsigned long long)__shfl_xor(pH, o, 64));
+    }
+    lprev = __longlong_as_double((long long)pL);
+    const double h = __longlong_as_double((long long)(kInfBits - pH));
+    return cfl * h / ((double)D * lprev);
+  };
+  // a one-wave, one-patch workgroup is converged inside the patch's checks
+  // (the patch is the same in every lane): the time step is taken there, where
+  // the other modes take theirs
+  constexpr bool PIPE_IN = PIPE && G::PPW == 1 && G::NT == 64;
   // GATHER: the chunk's first two own planes, loaded as soon as the own
   // descriptor has been checked, while the neighbours' descriptors are still
   // on their way (for chunks whose march is fully unrolled; in the others the
@@ -194,11 +232,14 @@ __device__ __forceinline__ BodyOut update_body(
         }
       }
     }
-    const double dt = dev_dt ? dt_d : pd.dt;
+    double dt = dev_dt ? dt_d : pd.dt;
+    if constexpr (PIPE_IN) dt = pipe_dt();
     dt_used = dt;
     t_used = pd.t;
+    if constexpr (!PIPE || PIPE_IN) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) r[j] = T(dt / pd.dx[j]) * T(0.5);  // rusanov gives 2F
+      for (int j = 0; j < D; ++j) r[j] = T(dt / pd.dx[j]) * T(0.5);  // rusanov gives 2F
+    }
     hmin = pd.dx[0];
 #pragma unroll
     for (int j = 1; j < D; ++j) hmin = fmin(hmin, pd.dx[j]);
@@ -274,6 +315,17 @@ __device__ __forceinline__ BodyOut update_body(
       }
     }
   }
+  if constexpr (PIPE && !PIPE_IN) {
+    // several patches or waves per workgroup: the time step once the wave
+    // has left the patches' checks
+    const double dtp = pipe_dt();
+    dt_used = dtp;
+    // the volume widths read again (cached) rather than kept live through
+    // the neighbour checks
+    const fv_patch* pr = patches + (in_range ? b : 0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) r[j] = T(dtp / pr->dx[j]) * T(0.5);  // rusanov gives 2F
+  }
   if constexpr (G::PPW == 1) {
     // one patch per workgroup: every lane read the same descriptor, so its
     // values live in scalar registers
@@ -291,6 +343,7 @@ __device__ __forceinline__ BodyOut update_body(
     hmin = uni(hmin);
     dt_used = uni(dt_used);
     t_used = uni(t_used);
+    if constexpr (PIPE) lprev = uni(lprev);
   }
   // plane buffer [NV][NCELL]
   T* cell = lds + (ok && in_patch ? (slot * ZS + chunk) * G::SLOT : 0);
@@ -595,7 +648,7 @@ __device__ __forceinline__ BodyOut update_body(
       pw->dt = cfl * hmin / ((double)D * lam_b);
     }
   }
-  return BodyOut{lam_b, hmin, in_range, lead, slot};
+  return BodyOut{lam_b, hmin, in_range, lead, slot, dt_used, lprev};
 
 }
 
@@ -631,14 +684,48 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
   const int64_t i = wgi * G::PPW + slot;
   int64_t b = -1;
   if (slot < G::PPW && i < count) b = order ? order[order_base + i] : i;
-  const BodyOut bo =
-      update_body<T, D, P, 64, G::CHUNKS, GATHER, MODE == kLocalDt ? kLocalDt : kPlain, NTS,
-                  PUSH>(
+  constexpr int BMODE = MODE == kLocalDt ? kLocalDt : MODE == kPipelinedCfl ? kPipelinedCfl : kPlain;
+  const unsigned long long* prev =
+      MODE == kPipelinedCfl && !dt_dev
+          ? cflo.ws + (size_t)kCflSlot * kPipeSlots * (unsigned)((cflo.phase + 2) % 3)
+          : nullptr;
+  const BodyOut bo = update_body<T, D, P, 64, G::CHUNKS, GATHER, BMODE, NTS, PUSH>(
       patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo, gamma, dt_dev, max_eig,
-      cflo.cfl, b, lds, red, tid);
+      cflo.cfl, b, lds, red, tid, prev);
   const double lam_b = bo.lam;
   const double hmin = bo.hmin;
   const bool lead = bo.lead;
+  if constexpr (MODE == kPipelinedCfl) {
+    // Pipelined CFL step: fold this patch's maximum and smallest width into
+    // slot (workgroup mod kPipeSlots) of set `phase` (atomic maxima of IEEE
+    // bit patterns, as below; nothing waits for them: the next launch reads
+    // the set after this one has completed).  Workgroup 0 clears the set the
+    // previous launch read, which the next launch folds into, and reports
+    // the step.
+    unsigned long long* gw =
+        cflo.ws + (size_t)kCflSlot * (kPipeSlots * (unsigned)cflo.phase + blockIdx.x % kPipeSlots);
+    if (lead) {
+      __hip_atomic_fetch_max(&gw[kCflWord], (unsigned long long)__double_as_longlong(lam_b),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(&gw[2 * kCflWord],
+                             kInfBits - (unsigned long long)__double_as_longlong(hmin),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (blockIdx.x == 0) {
+      unsigned long long* sc =
+          cflo.ws + (size_t)kCflSlot * kPipeSlots * (unsigned)((cflo.phase + 1) % 3);
+      if (tid < kPipeSlots) {
+        __hip_atomic_store(&sc[(size_t)kCflSlot * tid + kCflWord], 0ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&sc[(size_t)kCflSlot * tid + 2 * kCflWord], 0ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (tid == 0) {
+        if (cflo.dt_used) *cflo.dt_used = bo.dt;
+        if (cflo.lambda_out && !dt_dev) *cflo.lambda_out = bo.lprev;
+      }
+    }
+  }
   if constexpr (MODE == kGlobalCfl) {
     // Fused CFL step.  Patch maxima and smallest volume widths are folded
     // with device-scope atomic maxima of IEEE bit patterns (values >= 0 or
@@ -904,6 +991,16 @@ int launch_step_gather(const fv_patch* patches, int64_t n, const int64_t* neighb
 }
 
 template <typename T>
+int launch_step_pipelined(const fv_patch* patches, int64_t n, const int64_t* neighbours,
+                          const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int dim,
+                          int p, double gamma, double* max_eig, const CflOut& cflo,
+                          hipStream_t st) {
+  return dispatch<T, true, kPipelinedCfl>(patches, n, neighbours, qin, qin_len, qout, qout_len, 0,
+                                          dim, p, gamma, cflo.dt_in, max_eig, cflo, nullptr, 0, n,
+                                          st);
+}
+
+template <typename T>
 int launch_step_halo(const fv_patch* patches, int64_t n, const int64_t* neighbours,
                      const T* qin, int64_t qin_len, T* qout, int64_t qout_len, int dim, int p,
                      double gamma, const double* dt_dev, double* max_eig, const CflOut& cflo,
@@ -998,6 +1095,9 @@ int launch_step_local(const fv_patch* patches, int64_t n, const int64_t* neighbo
   template int launch_step_gather<T>(const fv_patch*, int64_t, const int64_t*, const T*,        \
                                      int64_t, T*, int64_t, int, int, double, const double*,     \
                                      double*, const CflOut&, hipStream_t);                      \
+  template int launch_step_pipelined<T>(const fv_patch*, int64_t, const int64_t*, const T*,     \
+                                        int64_t, T*, int64_t, int, int, double, double*,        \
+                                        const CflOut&, hipStream_t);                            \
   template int launch_step_local<T>(const fv_patch*, int64_t, const int64_t*,                   \
                                     const fv_mixed_plan&, const T*, int64_t, T*, int64_t,       \
                                     double, double, double*, int, int, hipStream_t);

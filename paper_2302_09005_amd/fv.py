@@ -93,6 +93,13 @@ def library():
     lib.fv_step_halo.argtypes = [vp, i64, vp, vp, i64, vp, i64, i32, i32, i32, i32, f64, f64, vp,
                                  vp, vp, vp, vp, i64, vp]
     lib.fv_step_halo.restype = i32
+    lib.fv_step_gather_pipelined.argtypes = [vp, i64, vp, vp, i64, vp, i64, i32, i32, i32, f64,
+                                             f64, i32, vp, vp, vp, vp, vp, i64, vp]
+    lib.fv_step_gather_pipelined.restype = i32
+    lib.fv_step_gather_pipelined_f32.argtypes = lib.fv_step_gather_pipelined.argtypes
+    lib.fv_step_gather_pipelined_f32.restype = i32
+    lib.fv_step_pipelined_workspace_words.argtypes = [i64, i32, i32]
+    lib.fv_step_pipelined_workspace_words.restype = i64
     lib.fv_step_gather_noalloc.argtypes = lib.fv_step_gather.argtypes[:-3] + [vp]
     lib.fv_step_gather_noalloc.restype = i32
     lib.fv_step_workspace_words.argtypes = [i64, i32, i32]
@@ -294,6 +301,50 @@ def step_gather(patches, neighbours, q_in, q_out, dt, dt_next, workspace, *, dim
               q_out.numel(), dim, p, dim + 2, float(gamma), float(cfl), _ptr(dt), _ptr(max_eig),
               _ptr(dt_next), _ptr(lambda_out), _ptr(workspace), workspace.numel(),
               _stream(stream)))
+
+
+def pipelined_workspace_words(n, dim, p):
+    """Words of the zero-initialised int64 workspace fv_step_gather_pipelined needs."""
+    return int(library().fv_step_pipelined_workspace_words(n, dim, p))
+
+
+def _pipelined_args(patches, neighbours, q_in, q_out, workspace, dim, p, gamma, cfl, phase,
+                    dt_in, dt_used, max_eig, lambda_out):
+    """Checks the arguments of fv_step_gather_pipelined[_f32]; returns the
+    entry point and its argument tuple (without the stream)."""
+    import torch
+    sfx = _same_state(q_in, q_out)
+    for t, name in ((dt_in, "dt_in"), (dt_used, "dt_used"), (max_eig, "max_eig"),
+                    (lambda_out, "lambda_out")):
+        if t is not None:
+            _dev_f64(t, name)
+    if phase not in (0, 1, 2):
+        raise ValueError("phase must be 0, 1 or 2")
+    n = _n_patches(patches)
+    need = pipelined_workspace_words(n, dim, p)
+    if not (workspace.is_cuda and workspace.dtype in (torch.int64, torch.uint64)
+            and workspace.numel() >= need and workspace.is_contiguous()):
+        raise TypeError(f"workspace must be a contiguous 64-bit integer device tensor of "
+                        f">= {need} words")
+    _dev_nbr(neighbours, n, dim)
+    if max_eig is not None and max_eig.numel() < n:
+        raise ValueError("max_eig needs one entry per patch")
+    fn = getattr(library(), "fv_step_gather_pipelined" + sfx)
+    return fn, (_ptr(patches), n, _ptr(neighbours), _ptr(q_in), q_in.numel(), _ptr(q_out),
+                q_out.numel(), dim, p, dim + 2, float(gamma), float(cfl), int(phase),
+                _ptr(dt_in), _ptr(dt_used), _ptr(max_eig), _ptr(lambda_out), _ptr(workspace),
+                workspace.numel())
+
+
+def step_gather_pipelined(patches, neighbours, q_in, q_out, workspace, *, dim, p, phase,
+                          dt_in=None, dt_used=None, gamma=1.4, cfl=0.4, max_eig=None,
+                          lambda_out=None, stream=None):
+    """fv_step_gather_pipelined[_f32]: the fused step with the CFL reduction
+    done by the next call (phase 0, 1, 2, 0, ... over a run; dt_in on the
+    first call only)."""
+    fn, args = _pipelined_args(patches, neighbours, q_in, q_out, workspace, dim, p, gamma, cfl,
+                               phase, dt_in, dt_used, max_eig, lambda_out)
+    _check(fn(*args, _stream(stream)))
 
 
 def step_halo(patches, neighbours, q_in, q_out, dt, dt_next, workspace, *, dim, p, gamma=1.4,
@@ -660,7 +711,10 @@ class Stepper:
     (the paper's interface, halo kept consistent by a separate pass).  mode
     "halo_step": the same blocks and results as "halo" in ONE launch per step
     (fv_step_halo: the exchange pushed into the output halos, the next CFL
-    step from the fused reduction; float64 state).  The time
+    step from the fused reduction; float64 state).  mode "pipelined": the
+    results of "fused" in ONE launch of fv_step_gather_pipelined per step,
+    each launch taking its time step from the maxima the previous one folded
+    (the first from the constructor's CFL step).  The time
     step always comes from the per-patch maxima of the previous step's state;
     nothing leaves the device.  q0 must be laid out for the mode
     (workloads.PatchGrid.pack for "halo", pack_compact otherwise).
@@ -669,8 +723,9 @@ class Stepper:
     def __init__(self, desc, neighbours, q0, *, dim, p, gamma=1.4, cfl=0.4, mode="fused",
                  device="cuda", dtype=None):
         import torch
-        if mode not in ("fused", "gather", "halo", "halo_step"):
-            raise ValueError("mode must be 'fused', 'gather', 'halo' or 'halo_step'")
+        if mode not in ("fused", "gather", "halo", "halo_step", "pipelined"):
+            raise ValueError("mode must be 'fused', 'gather', 'halo', 'halo_step' or "
+                             "'pipelined'")
         if mode == "halo_step" and dtype not in (None, np.float64):
             raise ValueError("mode 'halo_step' takes float64 state")
         desc = np.ascontiguousarray(desc, dtype=PATCH_DTYPE)
@@ -680,7 +735,7 @@ class Stepper:
         self.mode = mode
         self.halo = mode in ("halo", "halo_step")
         # one launch per step that also computes the next step's dt
-        self.one_launch = mode in ("fused", "halo_step")
+        self.one_launch = mode in ("fused", "halo_step", "pipelined")
         self.dim, self.p, self.gamma, self.cfl = dim, p, gamma, cfl
         self.n = desc.shape[0]
         self.patches = upload_patches(desc, device, dim=dim, p=p, q_out_halo=self.halo,
@@ -692,10 +747,14 @@ class Stepper:
         self.lam = torch.empty(1, dtype=torch.float64, device=device)
         self.dt = torch.empty(1, dtype=torch.float64, device=device)
         self.dt_next = torch.empty(1, dtype=torch.float64, device=device)
-        self.workspace = torch.zeros(max(3, step_workspace_words(self.n, dim, p)),
-                                     dtype=torch.int64, device=device)
+        words = (pipelined_workspace_words if mode == "pipelined" else step_workspace_words)(
+            self.n, dim, p)
+        self.workspace = torch.zeros(max(3, words), dtype=torch.int64, device=device)
         self._fused_args = None  # per buffer order: checked argument tuples of fv_step_gather
         self._parity = 0
+        self._k = 0  # steps taken (pipelined: the phase is _k % 3, dt given on step 0)
+        self._pipe_args = {}  # (state buffer, phase, first step) -> (entry point, arguments)
+        self.dt_used = torch.zeros(1, dtype=torch.float64, device=device)
         max_eigenvalue(self.patches, self.a, self.per_patch, dim=dim, p=p, gamma=gamma,
                        q_halo=self.halo)
         if self.one_launch:
@@ -710,6 +769,19 @@ class Stepper:
                      lambda_out=self.lam, dt_out=self.dt, stream=stream)
 
     def update(self, stream=None):
+        if self.mode == "pipelined":
+            key = (self.a.data_ptr(), self._k % 3, self._k == 0)
+            call = self._pipe_args.get(key)
+            if call is None:
+                # checked once per (buffer order, phase), then kept: eager
+                # stepping costs one call
+                call = _pipelined_args(self.patches, self.neighbours, self.a, self.b,
+                                       self.workspace, self.dim, self.p, self.gamma, self.cfl,
+                                       self._k % 3, self.dt if self._k == 0 else None,
+                                       self.dt_used, self.per_patch, self.lam)
+                self._pipe_args[key] = call
+            _check(call[0](*call[1], _stream(stream)))
+            return
         if self.mode == "halo_step":
             step_halo(self.patches, self.neighbours, self.a, self.b, self.dt, self.dt_next,
                       self.workspace, dim=self.dim, p=self.p, gamma=self.gamma, cfl=self.cfl,
@@ -756,10 +828,31 @@ class Stepper:
     def swap(self):
         """Swap the state buffers (and, fused, the dt buffers): the new state
         becomes the input of the next step."""
+        self._swap_roles()
+        self._k += 1
+
+    def _swap_roles(self):
         self.a, self.b = self.b, self.a
-        if self.one_launch:
+        if self.one_launch and self.mode != "pipelined":
             self.dt, self.dt_next = self.dt_next, self.dt
             self._parity ^= 1
+
+    def graph_period(self):
+        """Steps after which the launch arguments repeat (a graph of k steps
+        can be replayed back to back only when k is a multiple of it)."""
+        return 6 if self.mode == "pipelined" else 2
+
+    def position(self):
+        """Steps the host side has issued (update + swap pairs)."""
+        return self._k
+
+    def seek(self, k):
+        """Set the host side to step k without launching anything (after
+        graph replays moved the data there); k must be >= 1 in mode
+        'pipelined' once a step has been issued."""
+        if (k - self._k) % 2:
+            self._swap_roles()
+        self._k = k
 
     def step(self, stream=None):
         self.cfl_step(stream)
@@ -769,6 +862,8 @@ class Stepper:
 
     def last_dt(self):
         """Device tensor holding the time step used by the most recent step."""
+        if self.mode == "pipelined":
+            return self.dt_used
         return self.dt_next if self.one_launch else self.dt
 
     def state(self):

@@ -154,6 +154,32 @@ def test_step_workspace_size_and_rejection_on_host():
     assert lib.fv_step_gather(*bad, None, 0x5000, 4096, None) == fv.FV_EINVAL
 
 
+def test_step_pipelined_workspace_size_and_rejection_on_host():
+    lib = fv.library()
+    # three sets of 16 slots of 96 words (three 256-byte lines), any batch size
+    assert fv.pipelined_workspace_words(4096, 3, 8) == 3 * 16 * 96
+    assert fv.pipelined_workspace_words(100, 2, 8) == 3 * 16 * 96
+    assert fv.pipelined_workspace_words(262144, 3, 8) == 3 * 16 * 96
+    assert fv.pipelined_workspace_words(0, 3, 8) == 0
+    assert fv.pipelined_workspace_words(10, 3, 5) == 0
+    head = [0x1000, 4096, 0x2000, 0x10000, 1000, 0x100000, 1000, 3, 8, 5, 1.4, 0.4]
+    tail = [None, None, None, None, 0x5000]
+    f = lib.fv_step_gather_pipelined
+    assert f(*head, 0, *tail, 3 * 16 * 96 - 1, None) == fv.FV_EINVAL
+    assert "workspace" in lib.fv_last_error().decode()
+    for phase in (-1, 3):
+        assert f(*head, phase, *tail, 3 * 16 * 96, None) == fv.FV_EINVAL
+        assert "phase" in lib.fv_last_error().decode()
+    bad = list(head)
+    bad[11] = 0.0  # cfl
+    assert f(*bad, 0, *tail, 3 * 16 * 96, None) == fv.FV_EINVAL
+    assert lib.fv_step_gather_pipelined_f32(*head, 0, None, None, None, None, None,
+                                            3 * 16 * 96, None) == fv.FV_EINVAL  # null workspace
+    bad = list(head)
+    bad[1] = 0
+    assert f(*bad, 0, *tail, 3 * 16 * 96, None) == fv.FV_EINVAL
+
+
 def test_step_noalloc_refuses_batches_beyond_its_scratch_on_host():
     lib = fv.library()
     # 3-D 8^3: one patch per workgroup, 96 words per 64 workgroups plus 96
