@@ -981,11 +981,12 @@ def main():
                      "kernel": "fv_update_kernel<double,3,8,GATHER,PIPELINED_CFL,NTS=false>",
                      "bound_measured": "at 4096 patches the state (2 x 84 MB) stays in the 256 MB "
                                        "Infinity Cache and the kernel is bound inside the CU "
-                                       "(VALU busy 45 %, LDS bank conflicts 23 % of LDS cycles, "
-                                       "L2-to-fabric bytes 0.84 x algorithmic: "
+                                       "(VALU busy 47 %, waves waiting to issue 43 % and on "
+                                       "memory 25 % of their cycles, LDS bank conflicts 23 % of "
+                                       "LDS cycles, L2-to-fabric bytes 0.85 x algorithmic: "
                                        "profiles/kernel_counters_4096.md); out of cache "
                                        "(detail.out_of_cache_32768) the same kernel streams "
-                                       "from HBM at the same rate",
+                                       "from HBM at about the same rate",
                      "algorithmic_bytes_per_cell": bpc,
                      "kernel_avg_us": upd_ms.mean() * 1e3},
         "detail": {"update_cell_updates_per_s": cells / upd_s,
