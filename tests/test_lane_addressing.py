@@ -661,3 +661,72 @@ def test_push_stores_fill_every_face_halo_once(d, p, counts, bc):
     assert set(seen) == set(want)
     for k, v in want.items():
         assert seen[k] == v, (k, seen[k], v)
+
+
+# ---------------------------------------------------------------------------
+# CFL workspace words of the fused and the pipelined step (the kernels'
+# index arithmetic restated): every word a launch touches lies inside the
+# workspace the library asks for, and the pipelined step's three slot sets
+# keep their roles apart.
+# ---------------------------------------------------------------------------
+CFL_GROUP, CFL_WORD = 64, 32
+CFL_SLOT = 3 * CFL_WORD
+PIPE_SLOTS = 16
+
+
+def _fused_words(nwg):
+    """Words of fv_step_gather's tree: group slots (count, lambda, h) and the top count."""
+    ngrp = ceil_div(nwg, CFL_GROUP)
+    words = {0}  # top arrival count
+    for w in range(nwg):
+        g = w // CFL_GROUP
+        base = CFL_SLOT * (g + 1)
+        words |= {base, base + CFL_WORD, base + 2 * CFL_WORD}
+    return words, ngrp
+
+
+def _pipelined_words(nwg, phase, dt_given):
+    """(read, folded, cleared) words of one fv_step_gather_pipelined launch."""
+    rd = set()
+    if not dt_given:
+        base = CFL_SLOT * PIPE_SLOTS * ((phase + 2) % 3)
+        rd = {base + CFL_SLOT * s + k for s in range(PIPE_SLOTS) for k in (CFL_WORD, 2 * CFL_WORD)}
+    fold = set()
+    for w in range(nwg):
+        base = CFL_SLOT * (PIPE_SLOTS * phase + w % PIPE_SLOTS)
+        fold |= {base + CFL_WORD, base + 2 * CFL_WORD}
+    base = CFL_SLOT * PIPE_SLOTS * ((phase + 1) % 3)
+    clr = {base + CFL_SLOT * s + k for s in range(PIPE_SLOTS) for k in (CFL_WORD, 2 * CFL_WORD)}
+    return rd, fold, clr
+
+
+@pytest.mark.parametrize("d,p,n", [(3, 8, 4096), (3, 8, 4097), (3, 8, 1), (2, 16, 100),
+                                   (3, 4, 1000), (2, 4, 77), (3, 16, 130), (3, 8, 32768)])
+def test_cfl_workspace_words_stay_inside_the_workspace(d, p, n):
+    from paper_2302_09005_amd import fv
+    g = Geo(d, p)
+    nwg = ceil_div(n, g.ppw)
+    words, _ = _fused_words(nwg)
+    assert max(words) < fv.step_workspace_words(n, d, p)
+    need = fv.pipelined_workspace_words(n, d, p)
+    for phase in range(3):
+        for given in (False, True):
+            rd, fold, clr = _pipelined_words(nwg, phase, given)
+            assert max(rd | fold | clr) < need
+            # a launch reads one set, folds into another and clears the third
+            assert not (rd & fold) and not (rd & clr) and not (fold & clr)
+
+
+def test_pipelined_slot_sets_cycle_through_write_read_clear():
+    """Launch j folds into a set, launch j+1 reads it, launch j+2 clears it
+    and launch j+3 folds into it again: each set is cleared after its last
+    read and before its next fold."""
+    nwg = 300
+    for first in range(3):
+        roles = []
+        for j in range(9):
+            roles.append(_pipelined_words(nwg, (first + j) % 3, j == 0))
+        for j in range(1, 6):
+            assert roles[j][0] == roles[j - 1][1]      # j reads what j-1 folded
+            assert roles[j + 1][2] == roles[j - 1][1]  # j+1 clears it after that read
+            assert roles[j + 2][1] == roles[j + 1][2]  # j+2 folds into the cleared set
