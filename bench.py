@@ -43,6 +43,7 @@ METRIC = "cell-updates/s and % HBM peak, 3D Euler 8^3 patches, vs FP64 plain for
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fv_update_3d_p8_4096_traffic.txt")
 KERNEL_SOURCES = ["paper_2302_09005_amd/csrc/fv_update.hip",
+                  "paper_2302_09005_amd/csrc/fv_update_kernels.hpp",
                   "paper_2302_09005_amd/csrc/fv_euler.hpp",
                   "paper_2302_09005_amd/csrc/fv_internal.hpp"]
 

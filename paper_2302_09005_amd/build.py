@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libfv.so")
-SOURCES = ["fv_api.hip", "fv_update.hip", "fv_reduce.hip", "fv_halo.hip", "fv_learned_train.hip",
+SOURCES = ["fv_api.hip", "fv_update.hip", "fv_update_f32.hip", "fv_reduce.hip", "fv_halo.hip",
+           "fv_learned_train.hip",
            "fv_learned_infer.hip"]
 ARCH = os.environ.get("FV_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -30,7 +31,10 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=
 # Per-source flags.  The learned update keeps its matrix-core accumulators in
 # ordinary vector registers: tanh and the bfloat16 packing read every
 # accumulator, and accumulation registers would cost one move per value.
-SOURCE_FLAGS = {"fv_learned_infer.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+SOURCE_FLAGS = {"fv_learned_infer.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+                # the float32 update instances: the instruction-level-parallelism
+                # schedule (they keep four waves per SIMD with it)
+                "fv_update_f32.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def build(verbose: bool = False, extra=()) -> str:

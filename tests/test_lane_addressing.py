@@ -464,7 +464,7 @@ def test_mixed_waves_never_share_a_region():
             assert not overlap(l1, l2) and not overlap(r1, r2), (p, w, p2, w2)
     g8, g4 = mixed_geo(8), mixed_geo(4)
     assert g8.ppw * g8.slot != g4.ppw * g4.slot  # why the common stride matters
-    src = open(os.path.join(ROOT, "paper_2302_09005_amd", "csrc", "fv_update.hip")).read()
+    src = open(os.path.join(ROOT, "paper_2302_09005_amd", "csrc", "fv_update_kernels.hpp")).read()
     body = src[src.index("fv_mixed_kernel("):]
     body = body[:body.index("\n}\n")]
     assert body.count("lds + wave * kMixedWaveLds, red + wave * kMixedWaveRed") == 2
