@@ -162,11 +162,14 @@ __device__ void fill_bias(const float* __restrict__ blob, MlpBias& b, int tid, i
 }
 
 // Per-wave LDS of the network: the bfloat16 features of the 64 faces (the
-// layer-1 operand of both tiles) and the 4 outputs of each face.
+// layer-1 operand of both tiles).  A face's 4 outputs are written over its
+// first 16 bytes of features once its tile's layer-1 product has read them.
 struct MlpLds {
   alignas(16) bf16x8 x[64][2];   // [face][feature / 8]
-  alignas(16) float o[64][kNO];  // [face][output]
 };
+__device__ __forceinline__ float* mlp_out(MlpLds& s, int face) {
+  return reinterpret_cast<float*>(&s.x[face][0]);
+}
 
 // tanh of an accumulator tile, packed as the two k-step operands of the next
 // layer.
@@ -181,8 +184,8 @@ __device__ __forceinline__ void tanh_pack(const floatx16& c, bf16x8& k0, bf16x8&
 // The network on the 64 faces of this wave: lane l holds the normalised
 // features xh[16] of face l and receives its outputs o[4].  Wave-local: the
 // LDS traffic of one wave is ordered, so no workgroup barrier is needed.
-// tiles: 2, or 1 when faces 32..63 are not needed (their outputs are left
-// as they were); the same on every lane of the wave.
+// tiles: 2, or 1 when faces 32..63 are not needed (their o values are then
+// meaningless); the same on every lane of the wave.
 __device__ void mlp64(const MlpFrags& F, const MlpBias& B, MlpLds& s, int l,
                       const float (&xh)[kNF], float (&o)[kNO], int tiles = 2) {
   const int j = l & 31, h = l >> 5;
@@ -213,15 +216,23 @@ __device__ void mlp64(const MlpFrags& F, const MlpBias& B, MlpLds& s, int l,
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks)
       c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.w3[ks], h2[ks], c, 0, 0, 0);
-    if (h == 0) {  // rows 0..3 = the outputs of face 32 t + j
+    // rows 0..3 = the outputs of face 32 t + j, over its features (read by
+    // this tile's layer-1 product above, in program order; the fence keeps
+    // the compiler from moving the store above that read)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (h == 0) {
+      float* op = mlp_out(s, 32 * t + j);
 #pragma unroll
-      for (int m = 0; m < kNO; ++m) s.o[32 * t + j][m] = c[m];
+      for (int m = 0; m < kNO; ++m) op[m] = c[m];
     }
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  {
+    const float* op = mlp_out(s, l);
 #pragma unroll
-  for (int m = 0; m < kNO; ++m) o[m] = s.o[l][m];
+    for (int m = 0; m < kNO; ++m) o[m] = op[m];
+  }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
@@ -274,8 +285,11 @@ struct PatchLds {
   MlpLds mlp[NTH / 64];
 };
 
+// Four-wave workgroups: 39 KB of LDS lets four of them share a CU, and at
+// most 128 registers per thread lets their 16 waves be resident together
+// (4 per SIMD instead of 3).  Eight-wave workgroups run one per CU.
 template <int NTH>
-__global__ void __launch_bounds__(NTH)
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NTH == 256 ? 4 : 2)))
 learned_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
                       const int64_t* __restrict__ neighbours, const double* __restrict__ qin,
                       int64_t qin_len, double* __restrict__ qout, int64_t qout_len,

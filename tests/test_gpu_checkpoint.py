@@ -36,7 +36,7 @@ def _run(st, steps):
     return dts
 
 
-@pytest.mark.parametrize("mode", ["fused", "halo"])
+@pytest.mark.parametrize("mode", ["fused", "pipelined", "halo"])
 def test_global_step_resumes_bitwise(mode):
     """100 steps of 512 patches of 8^3 in one run == 50 steps, a host
     checkpoint of Q (and the time step it implies), then 50 more steps from a
