@@ -182,15 +182,21 @@ __device__ __forceinline__ BodyOut update_body(
   }
   double lprev = __builtin_nan("");
   // dt = cfl * min dx / (D * Lambda) over the previous launch's maxima,
-  // exactly as the fused step computes it at its end (every lane of the wave
-  // takes part)
+  // exactly as the fused step computes it at its end.  The slots sit in
+  // lanes 0 .. kPipeSlots-1, which are active wherever this runs (a patch's
+  // lanes start at lane 0), so they are folded among themselves and lane 0's
+  // result is given to the whole wave: lanes past a patch's last thread (17^2
+  // patches use 51 of 64) may be inactive here.
+  static_assert(kPipeSlots <= 64 && (kPipeSlots & (kPipeSlots - 1)) == 0, "slot fold");
   auto pipe_dt = [&]() -> double {
     if (!prev_slots) return dt_d;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int o = kPipeSlots / 2; o > 0; o >>= 1) {
       pL = max(pL, (unsigned long long)__shfl_xor(pL, o, 64));
       pH = max(pH, (unsigned long long)__shfl_xor(pH, o, 64));
     }
+    pL = (unsigned long long)uni((int64_t)pL);
+    pH = (unsigned long long)uni((int64_t)pH);
     lprev = __longlong_as_double((long long)pL);
     const double h = __longlong_as_double((long long)(kInfBits - pH));
     return cfl * h / ((double)D * lprev);
