@@ -78,7 +78,9 @@ int fv_supported(int dim, int p);
 
 /*
  * Kernel timing: until called again, every update launch of the calling
- * thread (fv_batch_update, fv_batch_update_gather, fv_step_gather) has its
+ * thread (fv_batch_update, fv_batch_update_gather, fv_step_gather,
+ * fv_step_gather_pipelined, fv_step_halo, fv_step_local, the learned
+ * update, and their _f32 forms) has its
  * dispatch record start_event when the kernel begins and stop_event when it
  * ends (hipEvent_t handles created by the caller), so the elapsed time
  * between them is the kernel's execution alone.  Pass two NULLs to stop.
