@@ -205,6 +205,7 @@ __device__ __forceinline__ BodyOut update_body(
   // (the patch is the same in every lane): the time step is taken there, where
   // the other modes take theirs
   constexpr bool PIPE_IN = PIPE && G::PPW == 1 && G::NT == 64;
+  static_assert(!PIPE_IN || G::TPP >= kPipeSlots, "the slot lanes are inside the patch");
   // GATHER: the chunk's first two own planes, loaded as soon as the own
   // descriptor has been checked, while the neighbours' descriptors are still
   // on their way (for chunks whose march is fully unrolled; in the others the
