@@ -942,9 +942,12 @@ def main():
         uneven_path(args.seed, tune=False, schedule=fixed, ramp_s=args.ramp_s))
     uneven32 = None
     if uneven is not None:
+        # the float instances have registers and a schedule of their own: tuned
+        # separately unless a schedule was given
         sched = tuple(uneven["schedule"]["chosen"])
-        uneven32 = uneven_path(args.seed, dtype=np.float32, tune=False, schedule=sched,
+        uneven32 = uneven_path(args.seed, dtype=np.float32, tune=fixed is None, schedule=sched,
                                ramp_s=args.ramp_s)
+        sched = tuple(uneven32["schedule"]["chosen"])
         errs = uneven_fp32_vs_fp64(args.seed, sched)
         uneven32["rel_l2_linf_vs_fp64_by_steps"] = {str(k): list(v) for k, v in errs.items()}
 
