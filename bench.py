@@ -248,6 +248,47 @@ def halo_step_path(grid, q, steps, warmup, ramp_s):
             "hbm_frac": (bpc + halo_bpc) * grid.cells / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
 
 
+def c1_path(seed, steps=100, ramp_s=0.3):
+    """The 2-D parity configuration: 64 patches of 16^2 (s = 4, dx = 1/128,
+    periodic, smooth density with seeded noise), the pipelined step captured
+    as graphs and timed as the headline, plus one eager update launch timed by
+    its dispatch events.  16 384 cell-updates per step: latency-bound, so its
+    throughput is reported but it is no roofline case."""
+    import torch
+    from paper_2302_09005_amd import fv
+    from paper_2302_09005_amd import workloads as W
+    grid, q = W.grid_2d_smooth(8, 16, seed=seed)
+    st = fv.Stepper(grid.descriptors(out_halo=False, in_halo=False), grid.neighbours(),
+                    grid.pack_compact(q), dim=2, p=16, mode="pipelined")
+    for _ in range(3):
+        st.step()
+    stream = torch.cuda.current_stream()
+    graph = StepGraphs(st, steps)
+    ramp(graph, ramp_s)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    graph.replay()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1)
+    graph.finish()
+    del graph
+    reps = 20
+    hip = HipEvents(reps)
+    for i in range(reps):
+        fv.set_launch_events(hip.start[i], hip.stop[i])
+        st.update()
+        st.swap()
+    fv.set_launch_events(None, None)
+    torch.cuda.synchronize()
+    kernel_us = float(np.median(hip.elapsed_ms()) * 1e3)
+    hip.destroy()
+    us = total * 1e3 / steps
+    return {"workload": "2d-euler-fp64-64x16^2-periodic", "patches": grid.n, "steps": steps,
+            "step_us": us, "cell_updates_per_s": grid.cells / (us * 1e-6),
+            "eager_kernel_us": kernel_us}
+
+
 def fused_step_path(grid, q, steps, warmup, ramp_s):
     """The headline workload with fv_step_gather (the CFL reduction finished
     at the end of each launch by the last workgroup to arrive) instead of the
@@ -952,6 +993,7 @@ def main():
         uneven32["rel_l2_linf_vs_fp64_by_steps"] = {str(k): list(v) for k, v in errs.items()}
 
     out_of_cache = out_of_cache_path(q, ramp_s=args.ramp_s)
+    c1 = c1_path(args.seed, ramp_s=args.ramp_s)
     learned_detail = None if args.no_learned else learned_path(args.seed)
     copy_gbs = copy_bandwidth()
 
@@ -1002,6 +1044,7 @@ def main():
                    "final_lambda": lam_final, "state_finite": finite,
                    "fused_step": fused,
                    "out_of_cache_32768": out_of_cache,
+                   "c1_2d_64x16": c1,
                    "plain_halo_path": plain,
                    "fp32_path": f32,
                    "uneven_batch": uneven,
