@@ -210,10 +210,18 @@ def plain_path(grid, q, steps):
     halo_ms = np.array([c.elapsed_time(e) for _, _, c, e in marks])
     cfl_ms = np.array([a.elapsed_time(b) for a, b, _, _ in marks])
     bpc = algorithmic_bytes_per_cell(grid.d, grid.p, grid.s, 8)
+    # the full step also moves every face-halo value once each way (read from
+    # the neighbour's interior, written into the halo): 2 * 2d p^(d-1) s 8 B
+    # per patch, 60 B per cell for 3-D 8^3 (170 B per cell in all)
+    full_bpc = bpc + 2 * 2 * grid.d * grid.p ** (grid.d - 1) * grid.s * 8 / grid.p ** grid.d
     return {"steps": steps, "cell_updates_per_s": grid.cells / (step_ms.mean() * 1e-3),
+            "step_us": float(step_ms.mean() * 1e3),
             "update_us": float(upd_ms.mean() * 1e3), "halo_fill_us": float(halo_ms.mean() * 1e3),
             "cfl_us": float(cfl_ms.mean() * 1e3),
-            "update_hbm_frac": bpc * grid.cells / (upd_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "update_hbm_frac": bpc * grid.cells / (upd_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "full_step_algorithmic_bytes_per_cell": full_bpc,
+            "full_step_hbm_frac": full_bpc * grid.cells / (step_ms.mean() * 1e-3) / 1e9
+            / HBM_PEAK_GBS}
 
 
 def halo_step_path(grid, q, steps, warmup, ramp_s):
