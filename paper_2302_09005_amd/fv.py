@@ -848,8 +848,11 @@ class Stepper:
 
     def seek(self, k):
         """Set the host side to step k without launching anything (after
-        graph replays moved the data there); k must be >= 1 in mode
-        'pipelined' once a step has been issued."""
+        graph replays moved the data there).  In mode 'pipelined' step 0 is
+        the one that takes the constructor's time step on a clean workspace,
+        so once a step has been issued k must be >= 1."""
+        if self.mode == "pipelined" and k < 1 and self._k > 0:
+            raise ValueError("a pipelined run cannot go back to its first step")
         if (k - self._k) % 2:
             self._swap_roles()
         self._k = k
