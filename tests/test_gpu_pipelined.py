@@ -78,12 +78,13 @@ def test_pipelined_run_equals_fused_run_bitwise(dim, p, counts, dtype):
     assert bool(torch.isfinite(st.state()).all())
 
 
-def test_headline_workload_100_steps_bitwise():
-    """The benchmarked workload (4096 x 8^3, FP64) over 100 steps: the same
-    state and time-step sequence as fv_step_gather."""
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_headline_workload_100_steps_bitwise(dtype):
+    """The benchmarked workload (4096 x 8^3, FP64 and FP32 state) over 100
+    steps: the same state and time-step sequence as fv_step_gather."""
     import torch
     grid, q = W.grid_3d_random_smooth(16, 8, seed=0)
-    ref, st = _pair(grid, q, None)
+    ref, st = _pair(grid, q, dtype)
     dts_ref, dts = [], []
     for _ in range(100):
         ref.step()
