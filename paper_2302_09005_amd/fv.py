@@ -753,7 +753,7 @@ class Stepper:
         self._fused_args = None  # per buffer order: checked argument tuples of fv_step_gather
         self._parity = 0
         self._k = 0  # steps taken (pipelined: the phase is _k % 3, dt given on step 0)
-        self._pipe_args = {}  # (state buffer, phase, first step) -> (entry point, arguments)
+        self._pipe_args = {}  # (state buffers, phase, first step) -> (entry point, arguments)
         self.dt_used = torch.zeros(1, dtype=torch.float64, device=device)
         max_eigenvalue(self.patches, self.a, self.per_patch, dim=dim, p=p, gamma=gamma,
                        q_halo=self.halo)
@@ -770,7 +770,7 @@ class Stepper:
 
     def update(self, stream=None):
         if self.mode == "pipelined":
-            key = (self.a.data_ptr(), self._k % 3, self._k == 0)
+            key = (self.a.data_ptr(), self.b.data_ptr(), self._k % 3, self._k == 0)
             call = self._pipe_args.get(key)
             if call is None:
                 # checked once per (buffer order, phase), then kept: eager
