@@ -277,20 +277,23 @@ def test_fused_step_matches_separate_launches_bitwise():
     assert st_a.lam.item() == st_a.per_patch.max().item()
 
 
-def test_fused_stepper_follows_replaced_buffers():
-    """The fused stepper's cached launch arguments follow a state buffer that
-    the caller replaced between steps (same values, new storage): bitwise the
-    same steps as an untouched stepper."""
+@pytest.mark.parametrize("mode", ["fused", "pipelined"])
+def test_fused_stepper_follows_replaced_buffers(mode):
+    """The one-launch steppers' cached launch arguments follow state buffers
+    that the caller replaced between steps (same values, new storage): bitwise
+    the same steps as an untouched stepper."""
     import torch
-    _say("[fused stepper, state buffer replaced between steps]")
+    _say(f"[{mode} stepper, state buffers replaced between steps]")
     grid, q = W.grid_3d_random_smooth(4, 8, seed=23)
     desc = grid.descriptors(out_halo=False, in_halo=False)
-    ref = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=3, p=8, mode="fused")
-    st = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=3, p=8, mode="fused")
-    for k in range(5):
+    ref = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=3, p=8, mode=mode)
+    st = fv.Stepper(desc, grid.neighbours(), grid.pack_compact(q), dim=3, p=8, mode=mode)
+    for k in range(7):
         ref.step()
         if k == 2:
             st.a = st.a.clone()
+        if k == 4:
+            st.b = torch.empty_like(st.b)
         st.step()
     torch.cuda.synchronize()
     assert torch.equal(ref.state(), st.state())
