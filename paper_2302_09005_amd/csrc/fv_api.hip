@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <new>
 
@@ -56,6 +57,17 @@ int launched(const char* what) {
 
 namespace fvk {
 LaunchEvents& launch_events() { return g_events; }
+
+int device_cu_count() {
+  static std::atomic<int> cu_count[64];
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  cus = cu_count[dev].load(std::memory_order_relaxed);
+  if (cus == 0 &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+    cu_count[dev].store(cus, std::memory_order_relaxed);
+  return cus;
+}
 }  // namespace fvk
 
 extern "C" {

@@ -123,6 +123,10 @@ struct LaunchEvents {
 };
 LaunchEvents& launch_events();
 
+// Compute units of the current device (queried once per device and kept; 0
+// if the query fails).
+int device_cu_count();
+
 // Time-step handling of an update launch.
 enum StepMode : int {
   kPlain = 0,      // dt from dt_dev or the descriptor; nothing else

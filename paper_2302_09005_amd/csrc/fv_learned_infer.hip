@@ -467,16 +467,8 @@ int launch_update_learned_2d(const fv_patch* patches, int64_t n, const int64_t* 
                              double threshold, double* max_eig, hipStream_t st) {
   if (n == 0) return 0;
   const LaunchEvents& ev = launch_events();
-  // eight waves per patch while every patch has a CU of its own (the CU
-  // count of each device is queried once and kept)
-  static std::atomic<int> cu_count[64];
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
-    cus = cu_count[dev].load(std::memory_order_relaxed);
-    if (cus == 0 &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-      cu_count[dev].store(cus, std::memory_order_relaxed);
-  }
+  // eight waves per patch while every patch has a CU of its own
+  const int cus = device_cu_count();
   if (n <= cus)
     hipExtLaunchKernelGGL(learned_update_kernel<512>, dim3((unsigned)n), dim3(512), 0, st,
                           ev.start, ev.stop, 0, patches, n, neighbours, qin, qin_len, qout,

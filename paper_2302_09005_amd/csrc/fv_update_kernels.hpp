@@ -45,6 +45,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <atomic>
+
 #include "fv_euler.hpp"
 #include "fv_internal.hpp"
 
@@ -114,7 +116,7 @@ __device__ __forceinline__ BodyOut update_body(
     const T* __restrict__ qin, int64_t qin_len, T* __restrict__ qout, int64_t qout_len,
     int out_halo, T gamma, const double* __restrict__ dt_dev, double* __restrict__ max_eig,
     double cfl, int64_t b, T* __restrict__ lds, T* __restrict__ red, int tid,
-    const unsigned long long* __restrict__ prev_slots = nullptr) {
+    const unsigned long long* __restrict__ prev_slots = nullptr, bool prio = false) {
   using G = Geo<D, P, NTW, ZS>;
   constexpr int S = G::S;
   constexpr int PC = G::PC;  // planes of a chunk (the last chunk may have fewer)
@@ -457,6 +459,22 @@ __device__ __forceinline__ BodyOut update_body(
   constexpr int UNROLL = PC <= 8 ? PC : 2;
 #pragma unroll UNROLL
   for (int pl = 0; pl < PC; ++pl) {
+    if (prio) {
+      // Issue priority falls from 3 to 0 as the march advances, so the waves
+      // that share a SIMD progress together: with the hardware's oldest-first
+      // arbitration alone, some race ahead and the last one marches alone at
+      // the end with nothing to hide its latency.  (Only when every
+      // workgroup of the launch is resident at once; the host decides.)
+      const int lv = (4 * pl) / PC;
+      if (pl == 0 || lv != (4 * (pl - 1)) / PC) {
+        switch (lv) {
+          case 0: __builtin_amdgcn_s_setprio(3); break;
+          case 1: __builtin_amdgcn_s_setprio(2); break;
+          case 2: __builtin_amdgcn_s_setprio(1); break;
+          default: __builtin_amdgcn_s_setprio(0); break;
+        }
+      }
+    }
     // the last chunk of an uneven split idles through its missing planes
     const bool live = !UNEVEN || pl < nrows;
     const bool run = UNI || (act && live);
@@ -681,7 +699,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
                  T* __restrict__ qout, int64_t qout_len, int out_halo, T gamma,
                  const double* __restrict__ dt_dev, double* __restrict__ max_eig,
                  CflOut cflo, const int64_t* __restrict__ order, int64_t order_base,
-                 int64_t count) {
+                 int64_t count, int prio) {
   using G = Geo<D, P>;
   __shared__ T lds[G::PPW * G::CHUNKS * G::SLOT];
   __shared__ T red[G::NRED];
@@ -700,7 +718,7 @@ fv_update_kernel(const fv_patch* __restrict__ patches, int64_t n,
           : nullptr;
   const BodyOut bo = update_body<T, D, P, 64, G::CHUNKS, GATHER, BMODE, NTS, PUSH>(
       patches, n, neighbours, qin, qin_len, qout, qout_len, out_halo, gamma, dt_dev, max_eig,
-      cflo.cfl, b, lds, red, tid, prev);
+      cflo.cfl, b, lds, red, tid, prev, prio != 0);
   const double lam_b = bo.lam;
   const double hmin = bo.hmin;
   const bool lead = bo.lead;
@@ -914,12 +932,27 @@ int launch(const fv_patch* patches, int64_t n, const int64_t* nbr, const T* qin,
   const int64_t blocks = (count + G::PPW - 1) / G::PPW;
   if (blocks == 0) return 0;
   const LaunchEvents& ev = launch_events();
+  auto kernel = fv_update_kernel<T, D, P, GATHER, MODE, NTS, PUSH>;
+  // The progress-based issue priority needs every workgroup resident at once
+  // (later workgroups would start at the top priority and starve older
+  // ones): workgroups per CU of this instance, queried once, times the CUs.
+  static std::atomic<int> per_cu{-1};
+  int wpc = per_cu.load(std::memory_order_relaxed);
+  if (wpc < 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel),
+                                                     G::NT, 0) != hipSuccess)
+      nb = 0;
+    per_cu.store(nb, std::memory_order_relaxed);
+    wpc = nb;
+  }
+  const int cus = device_cu_count();
+  const int prio = wpc > 0 && cus > 0 && blocks <= (int64_t)wpc * cus;
   // with caller events the dispatch packet itself records them, so they time
   // the kernel's execution and nothing around it
-  hipExtLaunchKernelGGL((fv_update_kernel<T, D, P, GATHER, MODE, NTS, PUSH>), dim3((unsigned)blocks),
-                        dim3(G::NT), 0, st, ev.start, ev.stop, 0, patches, n, nbr, qin, qin_len,
-                        qout, qout_len, out_halo, gamma, dt_dev, max_eig, cflo, order,
-                        order_base, count);
+  hipExtLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(G::NT), 0, st, ev.start, ev.stop, 0,
+                        patches, n, nbr, qin, qin_len, qout, qout_len, out_halo, gamma, dt_dev,
+                        max_eig, cflo, order, order_base, count, prio);
   return 0;
 }
 
